@@ -1,0 +1,283 @@
+"""Finite-volume scalar step on the dense grid, its Nusselt diagnostics and adjoint.
+
+Follows the paper's heat equation (Eq. 2) in integral form (Eq. 5) on the
+staggered grid (Sec. 2.2), the Euler-leapfrog step (Eq. 6) with the averaging
+step every N_p steps (Eq. 7), and the heat-flux Nusselt number (Eq. 22).
+
+Readings (each also listed in the design notes):
+* face value of the advected scalar: second-order central, the arithmetic
+  mean of the two neighbouring cells (the paper's code is fourth order);
+* diffusion: x and y explicit on the lagged level n-1 as in Eq. 6; the z part
+  moved to the new level n+1 and solved line by line (backward Euler over the
+  step's time span tau), which keeps the wall-clustered z grid stable;
+* the first step (n = 0) is forward Euler over dt with the same implicit z
+  part; the averaging step produces theta^{n+1} when (n+1) mod N_p = 0, n >= 1,
+  with its diffusion on level n-1 as written in Eq. 7;
+* z walls: Dirichlet (wall value at half a cell from the first centre) or
+  adiabatic; x and y periodic;
+* Nu(z) lives on the dense z faces; the plates use the half-cell gradient;
+  Nu_paper is the mean over the interior faces, Nu_vol the height-weighted sum.
+
+Array conventions: theta (nz, ny, nx); u (nz, ny, nx) on x-faces i (between
+cells i-1 and i, periodic); v likewise on y-faces; w (nz+1, ny, nx) on z-faces.
+Test infrastructure only; all arithmetic float64, plain NumPy.
+"""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+DIRICHLET = "dirichlet"
+ADIABATIC = "adiabatic"
+
+
+@dataclass
+class ScalarParams:
+    kappa: float                 # (Ra Pr)^(-1/2), Eq. 2
+    dt: float
+    n_avg: int = 50              # N_p of Eq. 7 (0 = never average)
+    t_bot: float = 1.0
+    t_top: float = 0.0
+    bc_bot: str = DIRICHLET
+    bc_top: str = DIRICHLET
+    ra: float = 1.0              # Ra and Pr enter Nu through (Ra Pr)^(1/2)
+    pr: float = 1.0
+
+    @staticmethod
+    def from_ra_pr(ra, pr, dt, **kw):
+        return ScalarParams(kappa=1.0 / math.sqrt(ra * pr), dt=dt, ra=ra, pr=pr, **kw)
+
+
+def step_kind(n, n_avg, dt):
+    """(tau, alpha_prev, alpha_cur, kind) of the step that makes theta^{n+1}.
+
+    n = 0: start-up, forward Euler over dt (Eq. 6 needs two levels);
+    (n+1) mod N_p = 0: averaging step of Eq. 7, 1.5 dt and (theta^{n-1}+theta^n)/2;
+    otherwise leapfrog of Eq. 6, 2 dt from theta^{n-1}."""
+    if n == 0:
+        return dt, 0.0, 1.0, "startup"
+    if n_avg > 0 and (n + 1) % n_avg == 0:
+        return 1.5 * dt, 0.5, 0.5, "average"
+    return 2.0 * dt, 1.0, 0.0, "leapfrog"
+
+
+# ------------------------------------------------------------------ operators
+def _areas(g):
+    ax = g.y.h[None, :, None] * g.z.h[:, None, None]       # x-face areas hy*hz
+    ay = g.x.h[None, None, :] * g.z.h[:, None, None]       # y-face areas hx*hz
+    az = g.x.h[None, :] * g.y.h[:, None]                   # z-face areas hx*hy (ny, nx)
+    return ax, ay, az
+
+
+def advection(g, th, u, v, w):
+    """C(theta) = -(1/V) sum of outward fluxes u_f A_f theta_f, theta_f = mean of the
+    two cells (Eq. 5, convective term); no flux through the z walls."""
+    ax, ay, az = _areas(g)
+    fx = u * 0.5 * (np.roll(th, 1, axis=2) + th) * ax       # face i: cells i-1, i
+    fy = v * 0.5 * (np.roll(th, 1, axis=1) + th) * ay
+    nz = th.shape[0]
+    fz = np.zeros((nz + 1,) + th.shape[1:])
+    fz[1:nz] = w[1:nz] * 0.5 * (th[:-1] + th[1:]) * az[None]
+    net = (np.roll(fx, -1, axis=2) - fx) + (np.roll(fy, -1, axis=1) - fy) + (fz[1:] - fz[:-1])
+    return -net / g.vol()
+
+
+def lap_h(g, th):
+    """Horizontal diffusion (1/V) sum over x and y faces of A_f (theta_R - theta_L)/dc_f."""
+    ax, ay, _ = _areas(g)
+    gx = (th - np.roll(th, 1, axis=2)) / g.x.dc[None, None, :] * ax
+    gy = (th - np.roll(th, 1, axis=1)) / g.y.dc[None, :, None] * ay
+    return ((np.roll(gx, -1, axis=2) - gx) + (np.roll(gy, -1, axis=1) - gy)) / g.vol()
+
+
+def z_matrix(g, tk, p):
+    """Tridiagonal (sub, diag, sup) of I - tk*Lz0 and the wall source bz with
+    Lz theta = Lz0 theta + bz (vertical diffusion per unit volume), tk = tau*kappa.
+
+    Row k: Lz0 couples theta_{k-1}, theta_k, theta_{k+1} through
+    (theta_{k+1}-theta_k)/(hz_k dc_{k+1}) - (theta_k-theta_{k-1})/(hz_k dc_k);
+    a Dirichlet wall adds -theta/(hz dc_wall) and the source T_wall/(hz dc_wall)."""
+    hz, dc = g.z.h, g.z.dc
+    nz = hz.size
+    sub = np.zeros(nz)
+    sup = np.zeros(nz)
+    sub[1:] = -tk / (hz[1:] * dc[1:nz])
+    sup[:-1] = -tk / (hz[:-1] * dc[1:nz])
+    diag = 1.0 - sub - sup
+    bz = np.zeros(nz)
+    if p.bc_bot == DIRICHLET:
+        diag[0] += tk / (hz[0] * dc[0])
+        bz[0] += p.t_bot / (hz[0] * dc[0])
+    if p.bc_top == DIRICHLET:
+        diag[-1] += tk / (hz[-1] * dc[nz])
+        bz[-1] += p.t_top / (hz[-1] * dc[nz])
+    return sub, diag, sup, bz
+
+
+def thomas(sub, diag, sup, r):
+    """Solve the tridiagonal system along axis 0 of r (classical Thomas algorithm)."""
+    n = diag.size
+    cp = np.empty(n)
+    dp = np.empty_like(r)
+    cp[0] = sup[0] / diag[0]
+    dp[0] = r[0] / diag[0]
+    for k in range(1, n):
+        den = diag[k] - sub[k] * cp[k - 1]
+        cp[k] = sup[k] / den
+        dp[k] = (r[k] - sub[k] * dp[k - 1]) / den
+    x = np.empty_like(r)
+    x[-1] = dp[-1]
+    for k in range(n - 2, -1, -1):
+        x[k] = dp[k] - cp[k] * x[k + 1]
+    return x
+
+
+def scalar_step(g, p, n, th_prev, th_cur, u, v, w):
+    """theta^{n+1} from theta^{n-1}, theta^n (Eqs. 6-7 with implicit z diffusion):
+
+    (I - tau kappa Lz0) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
+                                      + tau [C(theta^n) + kappa Lh(theta^lag) + kappa bz]
+    with theta^lag = theta^{n-1} (theta^0 at n = 0); th_prev is ignored at n = 0."""
+    tau, ap, ac, _ = step_kind(n, p.n_avg, p.dt)
+    lag = th_cur if n == 0 else th_prev
+    r = ac * th_cur + tau * (advection(g, th_cur, u, v, w) + p.kappa * lap_h(g, lag))
+    if n > 0:
+        r = r + ap * th_prev
+    sub, diag, sup, bz = z_matrix(g, tau * p.kappa, p)
+    r = r + (tau * p.kappa) * bz[:, None, None]
+    return thomas(sub, diag, sup, r)
+
+
+# ------------------------------------------------------------------- Nusselt
+def nusselt(g, p, th, w):
+    """Heat-flux Nusselt number on every dense z face (Eq. 22, instantaneous):
+
+    Nu_k = (Ra Pr)^(1/2) <w_k theta_f> - <(theta_k - theta_{k-1})/dc_k>,
+    <.> the area-weighted mean over x and y, theta_f the mean of the two cells;
+    at the plates the gradient uses the wall value and half a cell.
+    Returns (profile[0..nz], dict(nu_bot, nu_top, nu_vol, nu_paper, mean_theta)).
+    Sums are exact-rounded (math.fsum)."""
+    nz = th.shape[0]
+    area = g.area_xy()
+    atot = math.fsum(area.ravel())
+    dc = g.z.dc
+    sq = math.sqrt(p.ra * p.pr)
+    prof = np.zeros(nz + 1)
+    for k in range(1, nz):
+        conv = math.fsum((w[k] * 0.5 * (th[k - 1] + th[k]) * area).ravel()) / atot
+        grad = math.fsum(((th[k] - th[k - 1]) / dc[k] * area).ravel()) / atot
+        prof[k] = sq * conv - grad
+    if p.bc_bot == DIRICHLET:
+        prof[0] = -math.fsum(((th[0] - p.t_bot) / dc[0] * area).ravel()) / atot
+    if p.bc_top == DIRICHLET:
+        prof[nz] = -math.fsum(((p.t_top - th[-1]) / dc[nz] * area).ravel()) / atot
+    vol = g.vol()
+    out = dict(
+        nu_bot=prof[0],
+        nu_top=prof[nz],
+        nu_vol=math.fsum(dc * prof),
+        nu_paper=math.fsum(prof[1:nz]) / (nz - 1),
+        mean_theta=math.fsum((th * vol).ravel()) / math.fsum(vol.ravel()),
+    )
+    return prof, out
+
+
+# ------------------------------------------------------------------- adjoint
+def _lap_h_transpose(g, mu):
+    """Lh^T mu, written as the transpose of the face-flux form of ``lap_h``."""
+    ax, ay, _ = _areas(g)
+    q = mu / g.vol()
+    tx = ax / g.x.dc[None, None, :] * (np.roll(q, 1, axis=2) - q)   # face i: d/d theta_i
+    ty = ay / g.y.dc[None, :, None] * (np.roll(q, 1, axis=1) - q)
+    return (tx - np.roll(tx, -1, axis=2)) + (ty - np.roll(ty, -1, axis=1))
+
+
+def _advection_transpose(g, mu, u, v, w):
+    """C_u^T mu: each face f (cells L, R) gives s_f = u_f A_f (q_R - q_L)/2 to both cells."""
+    ax, ay, az = _areas(g)
+    q = mu / g.vol()
+    sx = 0.5 * u * ax * (q - np.roll(q, 1, axis=2))
+    sy = 0.5 * v * ay * (q - np.roll(q, 1, axis=1))
+    nz = mu.shape[0]
+    sz = np.zeros((nz + 1,) + mu.shape[1:])
+    sz[1:nz] = 0.5 * w[1:nz] * az[None] * (q[1:] - q[:-1])
+    return (sx + np.roll(sx, -1, axis=2)) + (sy + np.roll(sy, -1, axis=1)) + (sz[1:] + sz[:-1])
+
+
+def _advection_velocity_transpose(g, mu, th):
+    """Gradient of sum(mu * C_u(theta)) w.r.t. every dense face velocity:
+    A_f (theta_L + theta_R)/2 (q_R - q_L); zero on the z walls."""
+    ax, ay, az = _areas(g)
+    q = mu / g.vol()
+    gu = ax * 0.5 * (np.roll(th, 1, axis=2) + th) * (q - np.roll(q, 1, axis=2))
+    gv = ay * 0.5 * (np.roll(th, 1, axis=1) + th) * (q - np.roll(q, 1, axis=1))
+    nz = th.shape[0]
+    gw = np.zeros((nz + 1,) + th.shape[1:])
+    gw[1:nz] = az[None] * 0.5 * (th[:-1] + th[1:]) * (q[1:] - q[:-1])
+    return gu, gv, gw
+
+
+def step_vjp(g, p, n, th_cur, u, v, w, lam_next):
+    """Vector-Jacobian product of ``scalar_step`` at step n.
+
+    Given lam_next = dL/dtheta^{n+1}, returns (g_prev, g_cur, gu, gv, gw) with
+    mu = (I - tau kappa Lz0)^-T lam_next,
+    g_prev = a_p mu + tau kappa Lh^T mu          (n >= 1; zero at n = 0)
+    g_cur  = a_c mu + tau C_u^T mu (+ tau kappa Lh^T mu at n = 0)
+    g_vel  = tau dC/du^T mu on every dense face.
+    The tridiagonal transpose is formed explicitly (the matrix is not symmetric
+    on a stretched grid)."""
+    tau, ap, ac, _ = step_kind(n, p.n_avg, p.dt)
+    sub, diag, sup, _ = z_matrix(g, tau * p.kappa, p)
+    sub_t = np.zeros_like(sub)
+    sup_t = np.zeros_like(sup)
+    sub_t[1:] = sup[:-1]
+    sup_t[:-1] = sub[1:]
+    mu = thomas(sub_t, diag, sup_t, lam_next)
+    lh = (tau * p.kappa) * _lap_h_transpose(g, mu)
+    g_cur = ac * mu + tau * _advection_transpose(g, mu, u, v, w)
+    if n == 0:
+        g_cur = g_cur + lh
+        g_prev = np.zeros_like(mu)
+    else:
+        g_prev = ap * mu + lh
+    gu, gv, gw = _advection_velocity_transpose(g, mu, th_cur)
+    return g_prev, g_cur, tau * gu, tau * gv, tau * gw
+
+
+# ------------------------------------------------------------------- rollout
+def rollout(g, p, th0, u, v, w, nsteps, keep=False):
+    """theta^nsteps from theta^0 with a frozen dense velocity (all levels if keep)."""
+    levels = [th0]
+    prev, cur = th0, th0
+    for n in range(nsteps):
+        nxt = scalar_step(g, p, n, prev, cur, u, v, w)
+        prev, cur = cur, nxt
+        if keep:
+            levels.append(nxt)
+    return levels if keep else cur
+
+
+def rollout_loss_grad(g, p, th0, U, V, W, nsteps, target):
+    """Loss 0.5*||theta^N - target||^2 of refine + N steps, and its gradient
+    w.r.t. theta^0 and the coarse (U, V, W), by the discrete adjoint."""
+    from .refine import refine_velocity, refine_velocity_transpose
+    u, v, w = refine_velocity(g, U, V, W)
+    th = rollout(g, p, th0, u, v, w, nsteps, keep=True)
+    resid = th[nsteps] - target
+    loss = 0.5 * math.fsum((resid * resid).ravel())
+    lam = [np.zeros_like(th0) for _ in range(nsteps + 1)]
+    lam[nsteps] = resid.copy()
+    gu = np.zeros_like(u)
+    gv = np.zeros_like(v)
+    gw = np.zeros_like(w)
+    for n in range(nsteps - 1, -1, -1):
+        g_prev, g_cur, du, dv, dw = step_vjp(g, p, n, th[n], u, v, w, lam[n + 1])
+        lam[n] += g_cur
+        if n >= 1:
+            lam[n - 1] += g_prev
+        gu += du
+        gv += dv
+        gw += dw
+    gU, gV, gW = refine_velocity_transpose(g, gu, gv, gw)
+    return loss, lam[0], gU, gV, gW
