@@ -1,0 +1,215 @@
+/*
+ * mrscalar.h -- C ABI of the MI355X (gfx950) library for the dense-grid scalar
+ * step of the multiple-resolution finite-volume scheme (Chong, Ding & Xia,
+ * "Multiple-resolution scheme in finite-volume code for active or passive
+ * scalar turbulence").
+ *
+ * The scalar (temperature) lives on a dense grid, the velocity on a coarse
+ * grid whose faces are every M-th dense face (paper Sec. 3.1).  The library:
+ *   - refines the coarse staggered velocity onto the dense faces so that every
+ *     dense cell keeps zero net flux (Sec. 3.2, Eqs. 12-19);
+ *   - advances the cell-averaged scalar with finite-volume central advection
+ *     (Eqs. 2 and 5) in the Euler-leapfrog integrator with the averaging step
+ *     every N_p steps (Eqs. 6 and 7), x/y diffusion explicit on level n-1 and
+ *     z diffusion implicit on level n+1 (one tridiagonal solve per (x, y) line);
+ *   - reports the heat-flux Nusselt profile (Eq. 22) and the mean scalar;
+ *   - provides the discrete adjoint of the step and of the refinement.
+ *
+ * Conventions
+ *   Domain: x and y periodic, walls at z = zf[0] and z = zf[nz].
+ *   Arrays are C-contiguous with x fastest, indexed [z][y][x]:
+ *     dense scalar theta, u (x-faces), v (y-faces):  [nz][ny][nx]
+ *     dense w (z-faces, both walls included):        [nz+1][ny][nx]
+ *     coarse U, V:                                   [ncz][ncy][ncx]
+ *     coarse W (both walls included):                [ncz+1][ncy][ncx]
+ *   Face index i of u is the face at xf[i], between cells i-1 and i (cell -1
+ *   is the periodic image of cell nx-1); likewise v at yf[j] and w at zf[k].
+ *   Element type of every field pointer: double for MR_FP64 contexts, float
+ *   for MR_FP32 contexts.  Reductions (Nusselt, divergence) are always double.
+ *   Field pointers are device pointers owned by the caller, naturally aligned,
+ *   and must not alias unless a function says so.
+ *
+ * Streams: every call enqueues its kernels on the given hipStream_t (passed as
+ * void*, NULL = the null stream) and returns without waiting, except
+ * mr_nusselt with a non-NULL host_out, which waits for that stream.
+ * A context must not be used from two host threads at once.
+ *
+ * Errors: every function returns an int status (mr_status).  Arguments are
+ * checked on the host before anything is launched; a failed HIP call returns
+ * MR_EHIP and its hipError_t is kept for mr_last_hip_error.  Nothing aborts.
+ */
+#ifndef MRSCALAR_H
+#define MRSCALAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mr_ctx mr_ctx;
+
+typedef enum {
+  MR_OK = 0,
+  MR_EINVAL = -1,      /* invalid argument or descriptor */
+  MR_ESHAPE = -2,      /* sizes the kernels cannot handle */
+  MR_EHIP = -3,        /* a HIP runtime call failed */
+  MR_ENOMEM = -4,      /* device allocation failed */
+  MR_ENONFINITE = -5   /* a reduction met NaN or Inf */
+} mr_status;
+
+typedef enum { MR_FP64 = 0, MR_FP32 = 1 } mr_precision;
+typedef enum { MR_DIRICHLET = 0, MR_ADIABATIC = 1 } mr_wall_bc;
+
+/* Problem description (host memory; copied by mr_init). */
+typedef struct {
+  int32_t ncx, ncy, ncz;   /* coarse cells per axis (>= 3 where the refinement factor > 1) */
+  int32_t mx, my, mz;      /* refinement factors M_x, M_y, M_z (>= 1), Sec. 3.1 */
+  const double* xf;        /* nx+1 dense x faces, strictly increasing; period xf[nx]-xf[0] */
+  const double* yf;        /* ny+1 dense y faces, strictly increasing; period yf[ny]-yf[0] */
+  const double* zf;        /* nz+1 dense z faces, strictly increasing; walls at both ends */
+  int32_t bc_bot, bc_top;  /* scalar condition on each wall (mr_wall_bc) */
+  double t_bot, t_top;     /* wall values for MR_DIRICHLET */
+  double ra, pr;           /* diffusivity kappa = (Ra Pr)^(-1/2) (Eq. 2); Nu uses (Ra Pr)^(1/2) */
+  double dt;               /* fixed time step (> 0) */
+  int32_t n_avg;           /* averaging period N_p of Eq. 7 (0 = never) */
+  int32_t precision;       /* mr_precision of every field buffer */
+} mr_desc;
+
+/* Nusselt summary of one scalar field (Eq. 22, instantaneous). */
+typedef struct {
+  double nu_bot;      /* bottom plate: -<(theta_0 - T_bot)/(hz_0/2)> */
+  double nu_top;      /* top plate: -<(T_top - theta_{nz-1})/(hz_{nz-1}/2)> */
+  double nu_vol;      /* sum_k h_k Nu_k, h_k the distance between the cell centres around face k */
+  double nu_paper;    /* mean of Nu_k over the nz-1 interior faces */
+  double mean_theta;  /* volume-weighted mean scalar */
+} mr_nu;
+
+/* ---------------------------------------------------------------- setup */
+
+/* Validate the descriptor, build the grid tables on the host (refinement
+ * matrices R = A_s A^-1 per coarse cell and axis, Eq. 19; tridiagonal factors
+ * of the implicit z diffusion for the three step types) and upload them to the
+ * current HIP device.  R depends on the grid only and is computed once
+ * (Sec. 3.2).  Fails with MR_EINVAL on: a non-positive or inconsistent size,
+ * refinement factor < 1, fewer than 3 coarse cells on an axis with factor > 1,
+ * non-increasing faces, dt <= 0, Ra*Pr <= 0, an unknown wall condition or
+ * precision, or an explicit x/y diffusion number
+ * 2 dt kappa (4/hx_min^2 + 4/hy_min^2) above 1.  *out is set only on success. */
+int mr_init(const mr_desc* desc, mr_ctx** out);
+
+/* Free the context and its device tables.  NULL is accepted. */
+int mr_destroy(mr_ctx* ctx);
+
+/* --------------------------------------------------------- refinement (Sec. 3.2) */
+
+/* Coarse (U, V, W) -> dense (u, v, w).  Stages z, then y, then x: split the
+ * outer coarse face velocities with R (Eq. 19), then march each inner face
+ * from zero net outward flux of the sub-cell below it (Fig. 5a).  Every dense
+ * cell's net flux is the coarse cell's divergence for the last sub-cell of
+ * each coarse cell and zero (to rounding) for the others.  Inputs are not
+ * modified; outputs must not alias inputs. */
+int mr_interpolate_velocity(mr_ctx* ctx, const void* U, const void* V, const void* W,
+                            void* u, void* v, void* w, void* stream);
+
+/* Transpose of mr_interpolate_velocity: (gu, gv, gw) on the dense faces ->
+ * (gU, gV, gW) on the coarse faces, overwriting gU, gV, gW.  Every coarse face
+ * array is covered, the wall W planes included. */
+int mr_interpolate_velocity_backward(mr_ctx* ctx, const void* gu, const void* gv, const void* gw,
+                                     void* gU, void* gV, void* gW, void* stream);
+
+/* Discrete divergence check (Sec. 3.2 reports ~1e-17 in double precision).
+ * Writes to device memory dev_out[0] = max over dense cells of |net outward
+ * volume flux|, dev_out[1] = max over cells of |net flux| / (sum of |face
+ * fluxes| of the cell) (0 for a cell with no flux).  Always computed in double. */
+int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w,
+                  double* dev_out, void* stream);
+
+/* ------------------------------------------------------------ scalar step */
+
+/* theta^{n+1} from theta^{n-1} and theta^n (Eqs. 6-7, z diffusion implicit):
+ *   (I - tau kappa Lz) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
+ *        + tau [C_u(theta^n) + kappa Lh(theta^lag) + kappa b_z]
+ * with C_u the central-flux advection (face value = mean of the two cells, no
+ * flux through the walls), Lh the x/y diffusion, b_z the Dirichlet wall source,
+ * and per step type
+ *   n = 0 (start-up):          tau = dt,     a_p = 0,   a_c = 1,   lag = n
+ *   (n+1) mod N_p = 0, n >= 1: tau = 1.5 dt, a_p = 1/2, a_c = 1/2, lag = n-1
+ *   otherwise (leapfrog):      tau = 2 dt,   a_p = 1,   a_c = 0,   lag = n-1.
+ * th_prev is not read at n = 0 (may be NULL).  th_next must not alias th_prev or
+ * th_cur: callers rotate three buffers.  The tridiagonal elimination runs in
+ * double for both precisions. */
+int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_cur, void* th_next,
+                   const void* u, const void* v, const void* w, void* stream);
+
+/* ------------------------------------------------------------ adjoint */
+
+/* mu^n = (I - tau_n kappa Lz)^-T lam: the transposed implicit solve of step n.
+ * Seeds the reverse sweep with lam = dL/dtheta^{n+1}.  mu_out must not alias lam. */
+int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream);
+
+/* One fused reverse step.  With mu^m = (I - tau_m kappa Lz)^-T dL/dtheta^{m+1}:
+ *   lam^n = [mu_next != NULL] (a_p(n+1) mu^{n+1} + tau_{n+1} kappa Lh^T mu^{n+1})
+ *         + a_c(n) mu^n + tau_n C_u^T mu^n + [lam_add != NULL] lam_add
+ * is the complete dL/dtheta^n (lam_add: any direct loss gradient on theta^n).
+ * n >= 1: out = mu^{n-1} = (I - tau_{n-1} kappa Lz)^-T lam^n.
+ * n == 0: out = dL/dtheta^0 = lam^0 + tau_0 kappa Lh^T mu^0 (the start-up step
+ *         reads theta^0 for its diffusion too).
+ * out must not alias the inputs.  Velocity gradients are accumulated
+ * separately by mr_velocity_grad. */
+int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const void* mu_cur,
+                            const void* lam_add, void* out,
+                            const void* u, const void* v, const void* w, void* stream);
+
+/* Accumulate the dense face-velocity gradient of `count` steps (count <= 16):
+ *   g_f += sum_s tau_{n_s} A_f (theta_L + theta_R)/2 (mu_R/V_R - mu_L/V_L)
+ * on every dense face f with cells L and R (zero on the z walls), where
+ * theta = thetas[s] = theta^{n_s} and mu = mus[s] = mu^{n_s}.  steps, thetas
+ * and mus are host arrays (thetas/mus hold device pointers).  gu, gv, gw are
+ * read and written (+=). */
+int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps,
+                     const void* const* thetas, const void* const* mus,
+                     void* gu, void* gv, void* gw, void* stream);
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Heat-flux Nusselt number on every dense z face (Eq. 22):
+ *   Nu_k = (Ra Pr)^(1/2) <w_k (theta_{k-1} + theta_k)/2> - <(theta_k - theta_{k-1})/dc_k>
+ * with <.> the area-weighted x/y mean and dc_k the centre distance (half a
+ * cell at the plates, where the wall value replaces the missing cell).
+ * dev_profile (device, nz+6 doubles) receives Nu_0..Nu_nz followed by
+ * nu_bot, nu_top, nu_vol, nu_paper, mean_theta.  Sums are compensated
+ * (double-double) with a fixed reduction order, so results are bitwise
+ * reproducible.  If host_out is not NULL the summary is also copied there
+ * (the call then waits for the stream) and MR_ENONFINITE is returned when any
+ * value is NaN or Inf. */
+int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
+               mr_nu* host_out, void* stream);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Plain device copy of nbytes (multiple of 16, 16-byte aligned pointers) with
+ * the library's own streaming kernel: the bandwidth reference for profiles. */
+int mr_copy_probe(const void* src, void* dst, int64_t nbytes, void* stream);
+
+/* Host-only inspection of the tables mr_init would build (no GPU needed).
+ * axis 0/1/2 = x/y/z: R_out receives nc*m*3 doubles (R of every coarse cell,
+ * row-major [cell][sub][stencil]) and start_out nc int32 (first stencil cell,
+ * may be -1 on a periodic axis).  Either pointer may be NULL. */
+int mr_host_refinement_table(const mr_desc* desc, int32_t axis, double* R_out, int32_t* start_out);
+
+/* Host-only: the tridiagonal (sub, diag, sup) of I - tau_n kappa Lz and the wall
+ * source b_z (each nz doubles, any may be NULL) used by step n, and *tau_out. */
+int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, double* sup,
+                     double* bz, double* tau_out);
+
+/* Dense sizes of a context and its precision. */
+int mr_get_dims(const mr_ctx* ctx, int32_t* nx, int32_t* ny, int32_t* nz, int32_t* precision);
+
+const char* mr_status_string(int status);
+int mr_last_hip_error(const mr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRSCALAR_H */

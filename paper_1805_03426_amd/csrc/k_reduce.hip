@@ -1,0 +1,261 @@
+// Reductions: the discrete divergence check of the refined velocity
+// (Sec. 3.2), the heat-flux Nusselt profile and mean scalar (Eq. 22), and a
+// plain streaming copy used as the bandwidth reference.
+//
+// Every reduction is two-pass with a fixed partition and a fixed combining
+// order (wavefront shuffles, then LDS, then a single final block), so results
+// are bitwise reproducible.  Nusselt sums are double-double (error-free
+// two-sum), i.e. compensated.
+#include <algorithm>
+
+#include "mr_internal.h"
+
+namespace mr {
+namespace {
+
+// ------------------------------------------------------- double-double sums
+struct DD {
+  double s, c;
+};
+
+__device__ __forceinline__ DD dd_add(DD a, double b) {
+  const double t = a.s + b;
+  const double bp = t - a.s;
+  const double e = (a.s - (t - bp)) + (b - bp);
+  return {t, a.c + e};
+}
+
+__device__ __forceinline__ DD dd_merge(DD a, DD b) {
+  DD r = dd_add(a, b.s);
+  r.c += b.c;
+  return r;
+}
+
+__device__ __forceinline__ double shfl_down_d(double v, int off) {
+  return __shfl_down(v, off, kWave);
+}
+
+__device__ __forceinline__ DD wave_sum(DD v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    DD o{shfl_down_d(v.s, off), shfl_down_d(v.c, off)};
+    v = dd_merge(v, o);
+  }
+  return v;
+}
+
+// ------------------------------------------------------------- divergence
+constexpr int kDivBlocks = 2048;
+
+template <typename T>
+__global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const T* w, const double* hx,
+                                                  const double* hy, const double* hz, int nx, int ny,
+                                                  int nz, double* part) {
+  __shared__ double sh[2][256 / kWave];
+  const int nxy = nx * ny;
+  const int64_t cells = (int64_t)nxy * nz;
+  double mabs = 0.0, mrel = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cells;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / nxy);
+    const int ip = i == nx - 1 ? 0 : i + 1;
+    const int jp = j == ny - 1 ? 0 : j + 1;
+    const int c0 = k * nxy + j * nx;
+    const double ax = hy[j] * hz[k], ay = hx[i] * hz[k], az = hx[i] * hy[j];
+    const double ul = u[c0 + i], ur = u[c0 + ip];
+    const double vl = v[c0 + i], vr = v[k * nxy + jp * nx + i];
+    const double wl = w[c0 + i], wr = w[c0 + nxy + i];
+    const double dv = (ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az;
+    const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
+    mabs = fmax(mabs, fabs(dv));
+    if (tot > 0.0) mrel = fmax(mrel, fabs(dv) / tot);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    mabs = fmax(mabs, shfl_down_d(mabs, off));
+    mrel = fmax(mrel, shfl_down_d(mrel, off));
+  }
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sh[0][wv] = mabs;
+    sh[1][wv] = mrel;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)blockDim.x / kWave; ++q) {
+      mabs = fmax(mabs, sh[0][q]);
+      mrel = fmax(mrel, sh[1][q]);
+    }
+    part[2 * blockIdx.x] = mabs;
+    part[2 * blockIdx.x + 1] = mrel;
+  }
+}
+
+__global__ void __launch_bounds__(kWave) max_final(const double* part, int n, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < n; q += kWave) {
+    a = fmax(a, part[2 * q]);
+    b = fmax(b, part[2 * q + 1]);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    a = fmax(a, shfl_down_d(a, off));
+    b = fmax(b, shfl_down_d(b, off));
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// ---------------------------------------------------------------- Nusselt
+// partials[(k*P + p)*6 + {conv s,c, grad s,c, mean s,c}]
+template <typename T>
+__global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const double* hx,
+                                                  const double* hy, int nx, int ny, int nz, int P,
+                                                  int dir_bot, int dir_top, double t_bot,
+                                                  double t_top, double* part) {
+  __shared__ DD sh[3][256 / kWave];
+  const int k = blockIdx.y;   // face 0..nz (mean of level k for k < nz)
+  const int p = blockIdx.x;
+  const int nxy = nx * ny;
+  const int per = (nxy + P - 1) / P;
+  const int lo = p * per, hi = min(nxy, lo + per);
+  DD conv{0.0, 0.0}, grad{0.0, 0.0}, mean{0.0, 0.0};
+  for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+    const int i = e % nx, j = e / nx;
+    const double area = hx[i] * hy[j];
+    if (k > 0 && k < nz) {
+      const double a = th[(k - 1) * nxy + e], b = th[k * nxy + e];
+      conv = dd_add(conv, (double)w[k * nxy + e] * (0.5 * (a + b)) * area);
+      grad = dd_add(grad, (b - a) * area);
+    } else if (k == 0) {
+      if (dir_bot) grad = dd_add(grad, ((double)th[e] - t_bot) * area);
+    } else {
+      if (dir_top) grad = dd_add(grad, (t_top - (double)th[(nz - 1) * nxy + e]) * area);
+    }
+    if (k < nz) mean = dd_add(mean, (double)th[k * nxy + e] * area);
+  }
+  conv = wave_sum(conv);
+  grad = wave_sum(grad);
+  mean = wave_sum(mean);
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sh[0][wv] = conv;
+    sh[1][wv] = grad;
+    sh[2][wv] = mean;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)blockDim.x / kWave; ++q) {
+      conv = dd_merge(conv, sh[0][q]);
+      grad = dd_merge(grad, sh[1][q]);
+      mean = dd_merge(mean, sh[2][q]);
+    }
+    double* o = part + ((size_t)k * P + p) * 6;
+    o[0] = conv.s; o[1] = conv.c;
+    o[2] = grad.s; o[3] = grad.c;
+    o[4] = mean.s; o[5] = mean.c;
+  }
+}
+
+__global__ void __launch_bounds__(256) nu_final(const double* part, int P, int nz,
+                                                const double* dcz, const double* hz, double atot,
+                                                double sq, double* mean_k, double* prof) {
+  for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
+    DD conv{0.0, 0.0}, grad{0.0, 0.0}, mean{0.0, 0.0};
+    for (int p = 0; p < P; ++p) {
+      const double* o = part + ((size_t)k * P + p) * 6;
+      conv = dd_merge(conv, DD{o[0], o[1]});
+      grad = dd_merge(grad, DD{o[2], o[3]});
+      mean = dd_merge(mean, DD{o[4], o[5]});
+    }
+    const double cs = conv.s + conv.c, gs = grad.s + grad.c;
+    prof[k] = sq * (cs / atot) - (gs / dcz[k]) / atot;
+    if (k < nz) mean_k[k] = (mean.s + mean.c) * hz[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DD vol{0.0, 0.0}, pap{0.0, 0.0}, mt{0.0, 0.0}, hsum{0.0, 0.0};
+    for (int k = 0; k <= nz; ++k) {
+      vol = dd_add(vol, dcz[k] * prof[k]);
+      if (k > 0 && k < nz) pap = dd_add(pap, prof[k]);
+      if (k < nz) {
+        mt = dd_add(mt, mean_k[k]);
+        hsum = dd_add(hsum, hz[k]);
+      }
+    }
+    prof[nz + 1] = prof[0];
+    prof[nz + 2] = prof[nz];
+    prof[nz + 3] = vol.s + vol.c;
+    prof[nz + 4] = nz > 1 ? (pap.s + pap.c) / (nz - 1) : 0.0;
+    prof[nz + 5] = (mt.s + mt.c) / (atot * (hsum.s + hsum.c));
+  }
+}
+
+// ------------------------------------------------------------------- copy
+__global__ void __launch_bounds__(256) copy_kernel(const int4* __restrict__ src, int4* __restrict__ dst,
+                                                   int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+hipError_t ensure_red(mr_ctx* c, size_t bytes) {
+  if (c->red_bytes >= bytes) return hipSuccess;
+  if (c->red) (void)hipFree(c->red);
+  c->red = nullptr;
+  c->red_bytes = 0;
+  hipError_t e = hipMalloc((void**)&c->red, bytes);
+  if (e == hipSuccess) c->red_bytes = bytes;
+  return e;
+}
+
+int nu_parts(const mr_ctx* c) {
+  const int64_t nxy = (int64_t)c->nx * c->ny;
+  int64_t P = (nxy + 256 * 16 - 1) / (256 * 16);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(P, 64));
+}
+
+}  // namespace
+
+hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void* w, double* out,
+                             hipStream_t s) {
+  const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
+  const int nb = (int)std::min<int64_t>(kDivBlocks, (cells + 255) / 256);
+  hipError_t e = ensure_red(c, sizeof(double) * 2 * kDivBlocks);
+  if (e != hipSuccess) return e;
+  if (c->precision == MR_FP64)
+    hipLaunchKernelGGL(div_kernel<double>, dim3(nb), dim3(256), 0, s, (const double*)u, (const double*)v,
+                       (const double*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->red);
+  else
+    hipLaunchKernelGGL(div_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)u, (const float*)v,
+                       (const float*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->red);
+  hipLaunchKernelGGL(max_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s) {
+  const int P = nu_parts(c);
+  const size_t part = (size_t)(c->nz + 1) * P * 6;
+  hipError_t e = ensure_red(c, sizeof(double) * (part + c->nz + 1));
+  if (e != hipSuccess) return e;
+  double* mean_k = c->red + part;
+  const dim3 grid(P, c->nz + 1);
+  const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
+  if (c->precision == MR_FP64)
+    hipLaunchKernelGGL(nu_partial<double>, grid, dim3(256), 0, s, (const double*)th, (const double*)w,
+                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, c->red);
+  else
+    hipLaunchKernelGGL(nu_partial<float>, grid, dim3(256), 0, s, (const float*)th, (const float*)w,
+                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, c->red);
+  hipLaunchKernelGGL(nu_final, dim3(1), dim3(256), 0, s, (const double*)c->red, P, c->nz, c->dcz,
+                     c->hz64, c->atot, sqrt(c->ra * c->pr), mean_k, prof);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t nbytes, hipStream_t s) {
+  const int64_t n = nbytes / 16;
+  if (n == 0) return hipSuccess;
+  const int nb = (int)std::min<int64_t>(65536, (n + 255) / 256);
+  hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(256), 0, s, (const int4*)src, (int4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace mr

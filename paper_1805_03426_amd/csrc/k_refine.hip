@@ -1,0 +1,422 @@
+// Divergence-free coarse -> dense refinement of the staggered velocity
+// (paper Sec. 3.2, Fig. 5a, Eqs. 12-19) and its transpose.
+//
+// Three stage kernels, z then y then x.  In each stage one thread owns one
+// coarse cell along the refined axis: it splits the two pairs of outer normal
+// face velocities of its column with R (Eq. 19, three-cell stencil) and marches
+// the inner faces of the refined axis upward from the coarse face below,
+// each from zero net outward flux of the sub-cell under it.  Intermediate
+// fields (after z, after z and y) are kept in a context-owned buffer.
+//
+// The transpose runs the stages in reverse order; a march becomes a suffix
+// sum inside each coarse cell, a split an R^T gather (no atomics: every output
+// value is written by exactly one thread, in a fixed order).
+#include <string.h>
+
+#include "mr_internal.h"
+
+namespace mr {
+namespace {
+
+template <typename T>
+struct RefArgs {
+  const T* in0;
+  const T* in1;
+  const T* in2;
+  T* out0;
+  T* out1;
+  T* out2;
+  T* out3;   // extra output of some transposed stages
+  T* out4;
+  Geom<T> g;
+  int nx, ny, nz, ncx, ncy, ncz, mx, my, mz;
+};
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+__device__ __forceinline__ T rdot(const T* R, const T q[3]) {
+  return R[0] * q[0] + R[1] * q[1] + R[2] * q[2];
+}
+
+// ---------------------------------------------------------------- forward
+// stage z: thread per coarse cell (I, J, K)
+template <typename T>
+__global__ void __launch_bounds__(256) stage_z(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, ncz = A.ncz, mz = A.mz;
+  const int ncxy = ncx * ncy;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * ncz) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, K = tid / ncxy;
+  const int Ip = wrap(I + 1, ncx), Jp = wrap(J + 1, ncy);
+  const T* U = A.in0;
+  const T* V = A.in1;
+  const T* W = A.in2;
+  T u0[3], u1[3], v0[3], v1[3];
+  for (int r = 0; r < 3; ++r) {
+    const int kc = A.g.sz[K * 3 + r];
+    u0[r] = U[kc * ncxy + J * ncx + I];
+    u1[r] = U[kc * ncxy + J * ncx + Ip];
+    v0[r] = V[kc * ncxy + J * ncx + I];
+    v1[r] = V[kc * ncxy + Jp * ncx + I];
+  }
+  const T iHX = A.g.iHX[I], iHY = A.g.iHY[J];
+  T wv = W[K * ncxy + J * ncx + I];
+  for (int m = 0; m < mz; ++m) {
+    const int k = K * mz + m;
+    const T* R = A.g.Rz + (K * mz + m) * 3;
+    const T a = rdot(R, u0), b = rdot(R, u1), c = rdot(R, v0), d = rdot(R, v1);
+    A.out0[k * ncxy + J * ncx + I] = a;
+    A.out1[k * ncxy + J * ncx + I] = c;
+    A.out2[k * ncxy + J * ncx + I] = wv;
+    if (m < mz - 1) wv = wv - A.g.hz[k] * ((b - a) * iHX + (d - c) * iHY);
+  }
+  if (K == ncz - 1) A.out2[A.nz * ncxy + J * ncx + I] = W[ncz * ncxy + J * ncx + I];
+}
+
+// stage y: thread per (coarse I, coarse J, dense k)
+template <typename T>
+__global__ void __launch_bounds__(256) stage_y(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, nz = A.nz, my = A.my, ny = A.ny;
+  const int ncxy = ncx * ncy, nyx = ny * ncx;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * nz) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, k = tid / ncxy;
+  const int Ip = wrap(I + 1, ncx);
+  const T* Uz = A.in0;
+  const T* Vz = A.in1;
+  const T* Wz = A.in2;
+  T u0[3], u1[3], w0[3], w1[3];
+  for (int r = 0; r < 3; ++r) {
+    const int jc = A.g.sy[J * 3 + r];
+    u0[r] = Uz[k * ncxy + jc * ncx + I];
+    u1[r] = Uz[k * ncxy + jc * ncx + Ip];
+    w0[r] = Wz[k * ncxy + jc * ncx + I];
+    w1[r] = Wz[(k + 1) * ncxy + jc * ncx + I];
+  }
+  const T iHX = A.g.iHX[I], ihz = A.g.ihz[k];
+  T vv = Vz[k * ncxy + J * ncx + I];
+  for (int m = 0; m < my; ++m) {
+    const int j = J * my + m;
+    const T* R = A.g.Ry + (J * my + m) * 3;
+    const T a = rdot(R, u0), b = rdot(R, u1), c = rdot(R, w0), d = rdot(R, w1);
+    A.out0[k * nyx + j * ncx + I] = a;
+    A.out1[k * nyx + j * ncx + I] = vv;
+    A.out2[k * nyx + j * ncx + I] = c;
+    if (k == nz - 1) A.out2[nz * nyx + j * ncx + I] = d;
+    if (m < my - 1) vv = vv - A.g.hy[j] * ((b - a) * iHX + (d - c) * ihz);
+  }
+}
+
+// stage x: thread per (coarse I, dense j, dense k)
+template <typename T>
+__global__ void __launch_bounds__(256) stage_x(RefArgs<T> A) {
+  const int ncx = A.ncx, nz = A.nz, mx = A.mx, ny = A.ny, nx = A.nx;
+  const int nyx = ny * ncx, nxy = nx * ny;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nyx * nz) return;
+  const int I = tid % ncx, j = (tid / ncx) % ny, k = tid / nyx;
+  const int jp = wrap(j + 1, ny);
+  const T* Uzy = A.in0;
+  const T* Vzy = A.in1;
+  const T* Wzy = A.in2;
+  T v0[3], v1[3], w0[3], w1[3];
+  for (int r = 0; r < 3; ++r) {
+    const int ic = A.g.sx[I * 3 + r];
+    v0[r] = Vzy[k * nyx + j * ncx + ic];
+    v1[r] = Vzy[k * nyx + jp * ncx + ic];
+    w0[r] = Wzy[k * nyx + j * ncx + ic];
+    w1[r] = Wzy[(k + 1) * nyx + j * ncx + ic];
+  }
+  const T ihy = A.g.ihy[j], ihz = A.g.ihz[k];
+  T uu = Uzy[k * nyx + j * ncx + I];
+  for (int m = 0; m < mx; ++m) {
+    const int i = I * mx + m;
+    const T* R = A.g.Rx + (I * mx + m) * 3;
+    const T a = rdot(R, v0), b = rdot(R, v1), c = rdot(R, w0), d = rdot(R, w1);
+    A.out0[k * nxy + j * nx + i] = uu;
+    A.out1[k * nxy + j * nx + i] = a;
+    A.out2[k * nxy + j * nx + i] = c;
+    if (k == nz - 1) A.out2[nz * nxy + j * nx + i] = d;
+    if (m < mx - 1) uu = uu - A.g.hx[i] * ((b - a) * ihy + (d - c) * ihz);
+  }
+}
+
+// -------------------------------------------------------------- transpose
+// Sum over the refined sub-faces p+1..m-1 of coarse cell I of g(I*m + q):
+// the adjoint of the increment that the march adds at sub-face p.
+template <typename T, typename F>
+__device__ __forceinline__ T suffix(int I, int m, int p, F g) {
+  T s = T(0);
+  for (int q = p + 1; q < m; ++q) s += g(I * m + q);
+  return s;
+}
+
+// R^T gather: sum over coarse cells I whose stencil holds cell c of
+// R_I[p][r] * val(I*m + p) with r the position of c in that stencil.
+template <typename T, typename F>
+__device__ __forceinline__ T gather(const T* R, const int* sidx, int nc, int m, bool periodic, int c, F val) {
+  if (m == 1) return val(c);
+  T acc = T(0);
+  const int lo = periodic ? c - 1 : max(0, c - 2);
+  const int hi = periodic ? c + 1 : min(nc - 1, c + 2);
+  for (int Iu = lo; Iu <= hi; ++Iu) {
+    const int I = periodic ? wrap(Iu, nc) : Iu;
+    for (int r = 0; r < 3; ++r) {
+      if (sidx[I * 3 + r] != c) continue;
+      for (int p = 0; p < m; ++p) acc += R[(I * m + p) * 3 + r] * val(I * m + p);
+    }
+  }
+  return acc;
+}
+
+// X1: thread per (coarse I, dense j, dense k).  in0..2 = gu, gv, gw (dense);
+// out0 = gUzy, out1 = gv_tot (dense), out2 = gw_tot (dense).
+template <typename T>
+__global__ void __launch_bounds__(256) tx_march(RefArgs<T> A) {
+  const int ncx = A.ncx, nz = A.nz, mx = A.mx, ny = A.ny, nx = A.nx;
+  const int nyx = ny * ncx, nxy = nx * ny;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nyx * nz) return;
+  const int I = tid % ncx, j = (tid / ncx) % ny, k = tid / nyx;
+  const int jm = wrap(j - 1, ny);
+  const T* gu = A.in0;
+  const T* gv = A.in1;
+  const T* gw = A.in2;
+  const T ihy = A.g.ihy[j], ihym = A.g.ihy[jm], ihz = A.g.ihz[k];
+  const T ihzm = k > 0 ? A.g.ihz[k - 1] : T(0);
+  T tot = T(0);
+  for (int p = 0; p < mx; ++p) {
+    const int i = I * mx + p;
+    const T hx = A.g.hx[i];
+    tot += gu[k * nxy + j * nx + i];
+    // adjoint of the march increment at sub-face p (zero for the last one)
+    const T c0 = -suffix<T>(I, mx, p, [&](int q) { return gu[k * nxy + j * nx + q]; });
+    const T cjm = -suffix<T>(I, mx, p, [&](int q) { return gu[k * nxy + jm * nx + q]; });
+    const T ckm = k > 0 ? -suffix<T>(I, mx, p, [&](int q) { return gu[(k - 1) * nxy + j * nx + q]; }) : T(0);
+    A.out1[k * nxy + j * nx + i] = gv[k * nxy + j * nx + i] + cjm * hx * ihym - c0 * hx * ihy;
+    A.out2[k * nxy + j * nx + i] = gw[k * nxy + j * nx + i] + ckm * hx * ihzm - c0 * hx * ihz;
+    if (k == nz - 1) A.out2[nz * nxy + j * nx + i] = gw[nz * nxy + j * nx + i] + c0 * hx * ihz;
+  }
+  A.out0[k * nyx + j * ncx + I] = tot;
+}
+
+// X2: thread per (coarse I, dense j, dense level k <= nz).  in1 = gv_tot,
+// in2 = gw_tot; out1 = gVzy, out2 = gWzy.
+template <typename T>
+__global__ void __launch_bounds__(256) tx_split(RefArgs<T> A) {
+  const int ncx = A.ncx, nz = A.nz, mx = A.mx, ny = A.ny, nx = A.nx;
+  const int nyx = ny * ncx, nxy = nx * ny;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nyx * (nz + 1)) return;
+  const int I = tid % ncx, j = (tid / ncx) % ny, k = tid / nyx;
+  const T* gv = A.in1;
+  const T* gw = A.in2;
+  A.out2[k * nyx + j * ncx + I] =
+      gather<T>(A.g.Rx, A.g.sx, ncx, mx, true, I, [&](int i) { return gw[k * nxy + j * nx + i]; });
+  if (k < nz)
+    A.out1[k * nyx + j * ncx + I] =
+        gather<T>(A.g.Rx, A.g.sx, ncx, mx, true, I, [&](int i) { return gv[k * nxy + j * nx + i]; });
+}
+
+// Y1: thread per (coarse I, coarse J, dense k).  in1 = gVzy; out0 = gUzy (+=),
+// out2 = gWzy (+=), out3 = gVz.
+template <typename T>
+__global__ void __launch_bounds__(256) ty_march(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, nz = A.nz, my = A.my, ny = A.ny;
+  const int ncxy = ncx * ncy, nyx = ny * ncx;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * nz) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, k = tid / ncxy;
+  const int Im = wrap(I - 1, ncx);
+  const T* gV = A.in1;
+  const T iHX = A.g.iHX[I], iHXm = A.g.iHX[Im], ihz = A.g.ihz[k];
+  const T ihzm = k > 0 ? A.g.ihz[k - 1] : T(0);
+  T tot = T(0);
+  for (int p = 0; p < my; ++p) {
+    const int j = J * my + p;
+    const T hy = A.g.hy[j];
+    tot += gV[k * nyx + j * ncx + I];
+    const T c0 = -suffix<T>(J, my, p, [&](int q) { return gV[k * nyx + q * ncx + I]; });
+    const T cim = -suffix<T>(J, my, p, [&](int q) { return gV[k * nyx + q * ncx + Im]; });
+    const T ckm = k > 0 ? -suffix<T>(J, my, p, [&](int q) { return gV[(k - 1) * nyx + q * ncx + I]; }) : T(0);
+    A.out0[k * nyx + j * ncx + I] += cim * hy * iHXm - c0 * hy * iHX;
+    A.out2[k * nyx + j * ncx + I] += ckm * hy * ihzm - c0 * hy * ihz;
+    if (k == nz - 1) A.out2[nz * nyx + j * ncx + I] += c0 * hy * ihz;
+  }
+  A.out3[k * ncxy + J * ncx + I] = tot;
+}
+
+// Y2: thread per (coarse I, coarse J, dense level k <= nz).  in0 = gUzy,
+// in2 = gWzy; out0 = gUz, out2 = gWz.
+template <typename T>
+__global__ void __launch_bounds__(256) ty_split(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, nz = A.nz, my = A.my, ny = A.ny;
+  const int ncxy = ncx * ncy, nyx = ny * ncx;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * (nz + 1)) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, k = tid / ncxy;
+  const T* gU = A.in0;
+  const T* gW = A.in2;
+  A.out2[k * ncxy + J * ncx + I] =
+      gather<T>(A.g.Ry, A.g.sy, ncy, my, true, J, [&](int j) { return gW[k * nyx + j * ncx + I]; });
+  if (k < nz)
+    A.out0[k * ncxy + J * ncx + I] =
+        gather<T>(A.g.Ry, A.g.sy, ncy, my, true, J, [&](int j) { return gU[k * nyx + j * ncx + I]; });
+}
+
+// Z1: thread per coarse cell (I, J, K).  in2 = gWz; out0 = gUz (+=),
+// out1 = gVz (+=), out2 = gW (coarse, final).
+template <typename T>
+__global__ void __launch_bounds__(256) tz_march(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, ncz = A.ncz, mz = A.mz;
+  const int ncxy = ncx * ncy;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * ncz) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, K = tid / ncxy;
+  const int Im = wrap(I - 1, ncx), Jm = wrap(J - 1, ncy);
+  const T* gWz = A.in2;
+  const T iHX = A.g.iHX[I], iHXm = A.g.iHX[Im], iHY = A.g.iHY[J], iHYm = A.g.iHY[Jm];
+  T tot = T(0);
+  for (int p = 0; p < mz; ++p) {
+    const int k = K * mz + p;
+    const T hz = A.g.hz[k];
+    tot += gWz[k * ncxy + J * ncx + I];
+    const T c0 = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + J * ncx + I]; });
+    const T cim = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + J * ncx + Im]; });
+    const T cjm = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + Jm * ncx + I]; });
+    A.out0[k * ncxy + J * ncx + I] += cim * hz * iHXm - c0 * hz * iHX;
+    A.out1[k * ncxy + J * ncx + I] += cjm * hz * iHYm - c0 * hz * iHY;
+  }
+  A.out2[K * ncxy + J * ncx + I] = tot;
+  if (K == ncz - 1) A.out2[ncz * ncxy + J * ncx + I] = gWz[A.nz * ncxy + J * ncx + I];
+}
+
+// Z2: thread per coarse cell (I, J, K).  in0 = gUz, in1 = gVz; out0 = gU, out1 = gV.
+template <typename T>
+__global__ void __launch_bounds__(256) tz_split(RefArgs<T> A) {
+  const int ncx = A.ncx, ncy = A.ncy, ncz = A.ncz, mz = A.mz;
+  const int ncxy = ncx * ncy;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= ncxy * ncz) return;
+  const int I = tid % ncx, J = (tid / ncx) % ncy, K = tid / ncxy;
+  const T* gU = A.in0;
+  const T* gV = A.in1;
+  A.out0[K * ncxy + J * ncx + I] =
+      gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gU[k * ncxy + J * ncx + I]; });
+  A.out1[K * ncxy + J * ncx + I] =
+      gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gV[k * ncxy + J * ncx + I]; });
+}
+
+// ---------------------------------------------------------------- launchers
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+RefArgs<T> ref_args(mr_ctx* c, const Geom<T>& g) {
+  RefArgs<T> a;
+  ::memset((void*)&a, 0, sizeof(a));
+  a.g = g;
+  a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
+  a.ncx = c->ncx; a.ncy = c->ncy; a.ncz = c->ncz;
+  a.mx = c->mx; a.my = c->my; a.mz = c->mz;
+  return a;
+}
+
+hipError_t ensure(void** buf, size_t* have, size_t need) {
+  if (*have >= need) return hipSuccess;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  hipError_t e = hipMalloc(buf, need);
+  if (e == hipSuccess) *have = need;
+  return e;
+}
+
+template <typename T>
+hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, const void* W,
+                    void* u, void* v, void* w, hipStream_t s) {
+  const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
+  const int64_t yc = (int64_t)c->nz * c->ny * c->ncx, yc1 = (int64_t)(c->nz + 1) * c->ny * c->ncx;
+  const size_t need = sizeof(T) * (size_t)(2 * zc + zc1 + 2 * yc + yc1);
+  hipError_t e = ensure(&c->interp_tmp, &c->interp_tmp_bytes, need);
+  if (e != hipSuccess) return e;
+  T* Uz = (T*)c->interp_tmp;
+  T* Vz = Uz + zc;
+  T* Wz = Vz + zc;
+  T* Uzy = Wz + zc1;
+  T* Vzy = Uzy + yc;
+  T* Wzy = Vzy + yc;
+  RefArgs<T> a = ref_args<T>(c, g);
+  a.in0 = (const T*)U; a.in1 = (const T*)V; a.in2 = (const T*)W;
+  a.out0 = Uz; a.out1 = Vz; a.out2 = Wz;
+  hipLaunchKernelGGL(stage_z<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+  a.in0 = Uz; a.in1 = Vz; a.in2 = Wz;
+  a.out0 = Uzy; a.out1 = Vzy; a.out2 = Wzy;
+  hipLaunchKernelGGL(stage_y<T>, dim3(nblk(zc)), dim3(256), 0, s, a);
+  a.in0 = Uzy; a.in1 = Vzy; a.in2 = Wzy;
+  a.out0 = (T*)u; a.out1 = (T*)v; a.out2 = (T*)w;
+  hipLaunchKernelGGL(stage_x<T>, dim3(nblk(yc)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t refine_transpose_t(mr_ctx* c, const Geom<T>& g, const void* gu, const void* gv,
+                              const void* gw, void* gU, void* gV, void* gW, hipStream_t s) {
+  const int64_t d0 = (int64_t)c->nz * c->ny * c->nx, d1 = (int64_t)(c->nz + 1) * c->ny * c->nx;
+  const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
+  const int64_t yc = (int64_t)c->nz * c->ny * c->ncx, yc1 = (int64_t)(c->nz + 1) * c->ny * c->ncx;
+  const size_t need = sizeof(T) * (size_t)(d0 + d1 + 2 * yc + yc1 + 2 * zc + zc1);
+  hipError_t e = ensure(&c->interp_bwd_tmp, &c->interp_bwd_tmp_bytes, need);
+  if (e != hipSuccess) return e;
+  T* gv_tot = (T*)c->interp_bwd_tmp;
+  T* gw_tot = gv_tot + d0;
+  T* gUzy = gw_tot + d1;
+  T* gVzy = gUzy + yc;
+  T* gWzy = gVzy + yc;
+  T* gUz = gWzy + yc1;
+  T* gVz = gUz + zc;
+  T* gWz = gVz + zc;
+  RefArgs<T> a = ref_args<T>(c, g);
+  // stage x transposed
+  a.in0 = (const T*)gu; a.in1 = (const T*)gv; a.in2 = (const T*)gw;
+  a.out0 = gUzy; a.out1 = gv_tot; a.out2 = gw_tot;
+  hipLaunchKernelGGL(tx_march<T>, dim3(nblk(yc)), dim3(256), 0, s, a);
+  a.in1 = gv_tot; a.in2 = gw_tot;
+  a.out1 = gVzy; a.out2 = gWzy;
+  hipLaunchKernelGGL(tx_split<T>, dim3(nblk(yc1)), dim3(256), 0, s, a);
+  // stage y transposed
+  a = ref_args<T>(c, g);
+  a.in1 = gVzy;
+  a.out0 = gUzy; a.out2 = gWzy; a.out3 = gVz;
+  hipLaunchKernelGGL(ty_march<T>, dim3(nblk(zc)), dim3(256), 0, s, a);
+  a = ref_args<T>(c, g);
+  a.in0 = gUzy; a.in2 = gWzy;
+  a.out0 = gUz; a.out2 = gWz;
+  hipLaunchKernelGGL(ty_split<T>, dim3(nblk(zc1)), dim3(256), 0, s, a);
+  // stage z transposed
+  a = ref_args<T>(c, g);
+  a.in2 = gWz;
+  a.out0 = gUz; a.out1 = gVz; a.out2 = (T*)gW;
+  hipLaunchKernelGGL(tz_march<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+  a = ref_args<T>(c, g);
+  a.in0 = gUz; a.in1 = gVz;
+  a.out0 = (T*)gU; a.out1 = (T*)gV;
+  hipLaunchKernelGGL(tz_split<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_refine(mr_ctx* c, const void* U, const void* V, const void* W, void* u, void* v,
+                         void* w, hipStream_t s) {
+  if (c->precision == MR_FP64) return refine_t<double>(c, c->g64, U, V, W, u, v, w, s);
+  return refine_t<float>(c, c->g32, U, V, W, u, v, w, s);
+}
+
+hipError_t launch_refine_transpose(mr_ctx* c, const void* gu, const void* gv, const void* gw,
+                                   void* gU, void* gV, void* gW, hipStream_t s) {
+  if (c->precision == MR_FP64) return refine_transpose_t<double>(c, c->g64, gu, gv, gw, gU, gV, gW, s);
+  return refine_transpose_t<float>(c, c->g32, gu, gv, gw, gU, gV, gW, s);
+}
+
+}  // namespace mr

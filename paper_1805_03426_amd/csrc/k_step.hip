@@ -1,0 +1,389 @@
+// Scalar step kernels: the fused forward step (Eqs. 5-7 with the z diffusion
+// implicit), its fused reverse step, the transposed solve that seeds the
+// reverse sweep, and the velocity-gradient accumulation.
+//
+// Layout of one workgroup: 64 lanes = 64 consecutive x columns (coalesced
+// x-fastest rows), one wavefront per z chunk of L levels, one y row.  Each
+// lane builds the right-hand side of its L cells from the stencil (x and y
+// neighbours from the cache, z neighbours carried in registers while it walks
+// up the chunk), runs the forward elimination and back substitution of its
+// chunk in double from zero boundary values, and keeps the L results in
+// registers.  The chunks of one column are then coupled through two scalars
+// per chunk (the elimination value entering from below, the solution value
+// entering from above) exchanged in LDS, and every cell gets its exact value
+// x = x_hat + D G + X B (G, B precomputed because the matrix is the same for
+// every line).  Each cell is read once and written once: no intermediate
+// field goes back to HBM.
+#include <string.h>
+
+#include "mr_internal.h"
+
+namespace mr {
+namespace {
+
+enum Mode { FWD = 0, BWD = 1, BWD0 = 2, SEED = 3 };
+
+template <typename T>
+struct LineArgs {
+  const T* a0;   // FWD: theta^{n-1} (lag);  BWD/BWD0: mu^n;          SEED: lambda
+  const T* a1;   // FWD: theta^n;           BWD/BWD0: mu^{n+1} or 0
+  const T* a2;   // BWD/BWD0: lam_add or 0
+  const T* u;
+  const T* v;
+  const T* w;
+  T* out;
+  Geom<T> g;
+  ZSys z;        // system solved for the output (FWD: step n; BWD: transpose of step n-1)
+  T ap, ac, tau, tk;   // FWD: step n;  BWD: a_c(n), tau_n, tau_n kappa (ap unused)
+  T ap1, tk1;          // BWD: a_p(n+1), tau_{n+1} kappa
+  int nx, ny, nz, nch;
+};
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, int idx) {
+  return p[idx];
+}
+
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
+  __shared__ double sh[4][kMaxChunks][kWave];
+  const int lane = threadIdx.x;
+  const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ntx = (nx + kWave - 1) / kWave;
+  const int t = xcd_remap(blockIdx.x, ntx * ny);
+  const int xt = t % ntx, j = t / ntx;
+  const int i_raw = xt * kWave + lane;
+  const bool act = i_raw < nx;
+  const int i = act ? i_raw : nx - 1;
+  const int im = i == 0 ? nx - 1 : i - 1;
+  const int ip = i == nx - 1 ? 0 : i + 1;
+  const int jm = j == 0 ? ny - 1 : j - 1;
+  const int jp = j == ny - 1 ? 0 : j + 1;
+  const int nxy = nx * ny;
+  const int k0 = c * L;
+  const int k1 = min(k0 + L, nz);
+  const Geom<T>& g = A.g;
+
+  const T ihx = g.ihx[i], ihxm = g.ihx[im], ihxp = g.ihx[ip];
+  const T idx0 = g.idxc[i], idx1 = g.idxc[ip];
+  const T ihy = g.ihy[j], ihym = g.ihy[jm], ihyp = g.ihy[jp];
+  const T idy0 = g.idyc[j], idy1 = g.idyc[jp];
+  const T half = T(0.5);
+
+  double d[L];
+  double dprev = 0.0;
+  // z ring of the field whose z neighbours the stencil needs (theta^n or mu^n)
+  T zm = T(0), zc = T(0), zp = T(0), w0 = T(0), w1 = T(0);
+  if (MODE != SEED) {
+    const T* f = MODE == FWD ? A.a1 : A.a0;
+    zc = ld(f, k0 * nxy + j * nx + i);
+    if (k0 > 0) zm = ld(f, (k0 - 1) * nxy + j * nx + i);
+    w0 = ld(A.w, k0 * nxy + j * nx + i);
+  }
+
+#pragma unroll
+  for (int kk = 0; kk < L; ++kk) {
+    const int k = k0 + kk;
+    if (k < k1) {
+      const int row = k * nxy + j * nx;
+      const int rm = k * nxy + jm * nx;
+      const int rp = k * nxy + jp * nx;
+      T r;
+      if (MODE == SEED) {
+        r = ld(A.a0, row + i);
+      } else {
+        const T* f = MODE == FWD ? A.a1 : A.a0;
+        zp = k + 1 < nz ? ld(f, row + nxy + i) : T(0);
+        w1 = ld(A.w, row + nxy + i);
+        const T fxm = ld(f, row + im), fxp = ld(f, row + ip);
+        const T fym = ld(f, rm + i), fyp = ld(f, rp + i);
+        const T u0 = ld(A.u, row + i), u1 = ld(A.u, row + ip);
+        const T v0 = ld(A.v, row + i), v1 = ld(A.v, rp + i);
+        const T ihz = g.ihz[k];
+        if (MODE == FWD) {
+          // central-flux advection of theta^n (face value = mean of the two cells)
+          const T fzl = k > 0 ? w0 * (zm + zc) : T(0);
+          const T fzr = k < nz - 1 ? w1 * (zc + zp) : T(0);
+          const T adv = -half * ((u1 * (zc + fxp) - u0 * (fxm + zc)) * ihx +
+                                 (v1 * (zc + fyp) - v0 * (fym + zc)) * ihy + (fzr - fzl) * ihz);
+          // lagged x/y diffusion of theta^{n-1}
+          const T pc = ld(A.a0, row + i);
+          const T pxm = ld(A.a0, row + im), pxp = ld(A.a0, row + ip);
+          const T pym = ld(A.a0, rm + i), pyp = ld(A.a0, rp + i);
+          const T lap = ((pxp - pc) * idx1 - (pc - pxm) * idx0) * ihx +
+                        ((pyp - pc) * idy1 - (pc - pym) * idy0) * ihy;
+          r = A.ap * pc + A.ac * zc + A.tau * adv + A.tk * lap;
+        } else {
+          // C_u^T mu^n: each face f (cells L, R) adds u_f (mu_R/h_R - mu_L/h_L)/2 to both cells
+          const T qc_x = zc * ihx, qc_y = zc * ihy, qc_z = zc * ihz;
+          T cz = T(0);
+          if (k > 0) cz += w0 * (qc_z - zm * g.ihz[k - 1]);
+          if (k < nz - 1) cz += w1 * (zp * g.ihz[k + 1] - qc_z);
+          const T cu = half * (u0 * (qc_x - fxm * ihxm) + u1 * (fxp * ihxp - qc_x) +
+                               v0 * (qc_y - fym * ihym) + v1 * (fyp * ihyp - qc_y) + cz);
+          r = A.ac * zc + A.tau * cu;
+          if (A.a1) {
+            // contribution of step n+1 through theta^n as its lagged level
+            const T nc = ld(A.a1, row + i);
+            const T nxm = ld(A.a1, row + im), nxp = ld(A.a1, row + ip);
+            const T nym = ld(A.a1, rm + i), nyp = ld(A.a1, rp + i);
+            const T qx = nc * ihx, qy = nc * ihy;
+            const T lt = ((nxm * ihxm - qx) * idx0 - (qx - nxp * ihxp) * idx1) +
+                         ((nym * ihym - qy) * idy0 - (qy - nyp * ihyp) * idy1);
+            r += A.ap1 * nc + A.tk1 * lt;
+          }
+          if (A.a2) r += ld(A.a2, row + i);
+          if (MODE == BWD0) {
+            // the start-up step also reads theta^0 for its diffusion
+            const T lt = ((fxm * ihxm - qc_x) * idx0 - (qc_x - fxp * ihxp) * idx1) +
+                         ((fym * ihym - qc_y) * idy0 - (qc_y - fyp * ihyp) * idy1);
+            r += A.tk * lt;
+          }
+        }
+        zm = zc;
+        zc = zp;
+        w0 = w1;
+      }
+      if (MODE == BWD0) {
+        if (act) A.out[row + i] = r;
+      } else {
+        const double rd = (double)r + A.z.tkb[k];
+        dprev = A.z.m[k] * rd + A.z.a[k] * dprev;
+        d[kk] = dprev;
+      }
+    }
+  }
+  if (MODE == BWD0) return;
+
+  // local back substitution from a zero value above the chunk
+  double xh = 0.0;
+#pragma unroll
+  for (int kk = L - 1; kk >= 0; --kk) {
+    const int k = k0 + kk;
+    if (k < k1) {
+      xh = d[kk] - A.z.cp[k] * xh;
+      d[kk] = xh;
+    }
+  }
+  sh[0][c][lane] = dprev;  // elimination value at the top of the chunk
+  sh[1][c][lane] = xh;     // local solution at the bottom of the chunk
+  __syncthreads();
+  if (c == 0) {
+    double D = 0.0;
+    for (int cc = 0; cc < A.nch; ++cc) {
+      sh[2][cc][lane] = D;
+      D = sh[0][cc][lane] + A.z.Fe[cc] * D;
+    }
+    double X = 0.0;
+    for (int cc = A.nch - 1; cc >= 0; --cc) {
+      sh[3][cc][lane] = X;
+      X = sh[1][cc][lane] + sh[2][cc][lane] * A.z.Gs[cc] + X * A.z.Bs[cc];
+    }
+  }
+  __syncthreads();
+  const double D = sh[2][c][lane];
+  const double X = sh[3][c][lane];
+#pragma unroll
+  for (int kk = 0; kk < L; ++kk) {
+    const int k = k0 + kk;
+    if (k < k1) {
+      const double x = d[kk] + D * A.z.G[k] + X * A.z.B[k];
+      if (act) A.out[k * nxy + j * nx + i] = (T)x;
+    }
+  }
+}
+
+template <typename T, int MODE>
+hipError_t launch_line(mr_ctx* c, const LineArgs<T>& a, hipStream_t s) {
+  const int ntx = (c->nx + kWave - 1) / kWave;
+  const dim3 grid((unsigned)(ntx * c->ny));
+  const dim3 block(kWave, c->nch);
+  switch (c->L) {
+#define MR_CASE(LL)                                                       \
+  case LL:                                                                \
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE>), grid, block, 0, s, a); \
+    break;
+    MR_CASE(8)
+    MR_CASE(16)
+    MR_CASE(24)
+    MR_CASE(32)
+    MR_CASE(40)
+#undef MR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+LineArgs<T> base_args(mr_ctx* c, const Geom<T>& g) {
+  LineArgs<T> a;
+  ::memset((void*)&a, 0, sizeof(a));
+  a.g = g;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  a.nch = c->nch;
+  return a;
+}
+
+template <typename T>
+hipError_t step_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* thp, const void* thc,
+                  void* thn, const void* u, const void* v, const void* w, hipStream_t s) {
+  const int kind = step_kind(n, c->n_avg);
+  LineArgs<T> a = base_args<T>(c, g);
+  a.a0 = (const T*)thp;
+  a.a1 = (const T*)thc;
+  a.u = (const T*)u;
+  a.v = (const T*)v;
+  a.w = (const T*)w;
+  a.out = (T*)thn;
+  a.z = c->zf[kind];
+  a.ap = (T)alpha_prev(kind);
+  a.ac = (T)alpha_cur(kind);
+  a.tau = (T)c->tau[kind];
+  a.tk = (T)(c->tau[kind] * c->kappa);
+  return launch_line<T, FWD>(c, a, s);
+}
+
+template <typename T>
+hipError_t seed_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* lam, void* mu, hipStream_t s) {
+  LineArgs<T> a = base_args<T>(c, g);
+  a.a0 = (const T*)lam;
+  a.out = (T*)mu;
+  a.z = c->zt[step_kind(n, c->n_avg)];
+  return launch_line<T, SEED>(c, a, s);
+}
+
+template <typename T>
+hipError_t bwd_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* mun, const void* muc,
+                 const void* lam_add, void* out, const void* u, const void* v, const void* w,
+                 hipStream_t s) {
+  const int kind = step_kind(n, c->n_avg);
+  LineArgs<T> a = base_args<T>(c, g);
+  a.a0 = (const T*)muc;
+  a.a1 = (const T*)mun;
+  a.a2 = (const T*)lam_add;
+  a.u = (const T*)u;
+  a.v = (const T*)v;
+  a.w = (const T*)w;
+  a.out = (T*)out;
+  a.ac = (T)alpha_cur(kind);
+  a.tau = (T)c->tau[kind];
+  a.tk = (T)(c->tau[kind] * c->kappa);
+  if (mun) {
+    const int k1 = step_kind(n + 1, c->n_avg);
+    a.ap1 = (T)alpha_prev(k1);
+    a.tk1 = (T)(c->tau[k1] * c->kappa);
+  }
+  if (n == 0) return launch_line<T, BWD0>(c, a, s);
+  a.z = c->zt[step_kind(n - 1, c->n_avg)];
+  return launch_line<T, BWD>(c, a, s);
+}
+
+// ------------------------------------------------------- velocity gradient
+constexpr int kMaxGradSteps = 16;
+
+template <typename T>
+struct GradArgs {
+  const T* th[kMaxGradSteps];
+  const T* mu[kMaxGradSteps];
+  T tau[kMaxGradSteps];
+  int count;
+  T* gu;
+  T* gv;
+  T* gw;
+  Geom<T> g;
+  int nx, ny, nz;
+};
+
+// One thread per dense cell (i, j, k) owns the faces on its low side: x-face i,
+// y-face j and, for k >= 1, z-face k.  The walls' z faces carry no advective
+// flux, so their gradient stays as it is.
+template <typename T>
+__global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int nxy = nx * ny;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nxy * nz) return;
+  const int i = tid % nx;
+  const int j = (tid / nx) % ny;
+  const int k = tid / nxy;
+  const int im = i == 0 ? nx - 1 : i - 1;
+  const int jm = j == 0 ? ny - 1 : j - 1;
+  const int row = k * nxy + j * nx;
+  const T half = T(0.5);
+  const T ihx = A.g.ihx[i], ihxm = A.g.ihx[im], ihy = A.g.ihy[j], ihym = A.g.ihy[jm];
+  const T ihz = A.g.ihz[k], ihzm = k > 0 ? A.g.ihz[k - 1] : T(0);
+  T su = T(0), sv = T(0), sw = T(0);
+  for (int s = 0; s < A.count; ++s) {
+    const T* th = A.th[s];
+    const T* mu = A.mu[s];
+    const T tc = th[row + i], mc = mu[row + i];
+    const T gx = half * (th[row + im] + tc) * (mc * ihx - mu[row + im] * ihxm);
+    const T gy = half * (th[k * nxy + jm * nx + i] + tc) * (mc * ihy - mu[k * nxy + jm * nx + i] * ihym);
+    su += A.tau[s] * gx;
+    sv += A.tau[s] * gy;
+    if (k > 0) {
+      const T gz = half * (th[row - nxy + i] + tc) * (mc * ihz - mu[row - nxy + i] * ihzm);
+      sw += A.tau[s] * gz;
+    }
+  }
+  A.gu[row + i] += su;
+  A.gv[row + i] += sv;
+  if (k > 0) A.gw[row + i] += sw;
+}
+
+template <typename T>
+hipError_t grad_t(mr_ctx* c, const Geom<T>& g, int count, const int64_t* steps,
+                  const void* const* thetas, const void* const* mus, void* gu, void* gv, void* gw,
+                  hipStream_t s) {
+  GradArgs<T> a;
+  ::memset((void*)&a, 0, sizeof(a));
+  for (int q = 0; q < count; ++q) {
+    a.th[q] = (const T*)thetas[q];
+    a.mu[q] = (const T*)mus[q];
+    a.tau[q] = (T)c->tau[step_kind(steps[q], c->n_avg)];
+  }
+  a.count = count;
+  a.gu = (T*)gu;
+  a.gv = (T*)gv;
+  a.gw = (T*)gw;
+  a.g = g;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
+  hipLaunchKernelGGL(grad_kernel<T>, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(mr_ctx* c, int64_t n, const void* thp, const void* thc, void* thn,
+                       const void* u, const void* v, const void* w, hipStream_t s) {
+  if (c->precision == MR_FP64) return step_t<double>(c, c->g64, n, thp, thc, thn, u, v, w, s);
+  return step_t<float>(c, c->g32, n, thp, thc, thn, u, v, w, s);
+}
+
+hipError_t launch_seed(mr_ctx* c, int64_t n, const void* lam, void* mu, hipStream_t s) {
+  if (c->precision == MR_FP64) return seed_t<double>(c, c->g64, n, lam, mu, s);
+  return seed_t<float>(c, c->g32, n, lam, mu, s);
+}
+
+hipError_t launch_step_backward(mr_ctx* c, int64_t n, const void* mun, const void* muc,
+                                const void* lam_add, void* out, const void* u, const void* v,
+                                const void* w, hipStream_t s) {
+  if (c->precision == MR_FP64) return bwd_t<double>(c, c->g64, n, mun, muc, lam_add, out, u, v, w, s);
+  return bwd_t<float>(c, c->g32, n, mun, muc, lam_add, out, u, v, w, s);
+}
+
+hipError_t launch_velocity_grad(mr_ctx* c, int count, const int64_t* steps,
+                                const void* const* thetas, const void* const* mus, void* gu,
+                                void* gv, void* gw, hipStream_t s) {
+  if (c->precision == MR_FP64) return grad_t<double>(c, c->g64, count, steps, thetas, mus, gu, gv, gw, s);
+  return grad_t<float>(c, c->g32, count, steps, thetas, mus, gu, gv, gw, s);
+}
+
+}  // namespace mr

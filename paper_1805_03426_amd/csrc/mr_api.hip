@@ -1,0 +1,601 @@
+// Host side of the C ABI: descriptor checks, grid tables, device uploads and
+// the exported entry points.  Tables follow the paper's grid design (Sec. 3.1),
+// the refinement matrices R = A_s A^-1 (Eqs. 12-19) and the implicit z
+// diffusion of the scalar step (Eqs. 2, 5-7).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <new>
+#include <vector>
+
+#include "mr_internal.h"
+
+namespace {
+
+using std::vector;
+
+struct Axis {
+  int n = 0, m = 1, nc = 0;
+  bool periodic = true;
+  vector<double> f, h, c, dc;  // faces, widths, centres, centre distances across faces
+};
+
+int build_axis(const double* faces, int n, int m, bool periodic, Axis& ax) {
+  if (!faces || n < 1 || m < 1 || n % m) return MR_EINVAL;
+  ax.n = n;
+  ax.m = m;
+  ax.nc = n / m;
+  ax.periodic = periodic;
+  ax.f.assign(faces, faces + n + 1);
+  for (int i = 0; i <= n; ++i)
+    if (!std::isfinite(ax.f[i])) return MR_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(ax.f[i + 1] > ax.f[i])) return MR_EINVAL;
+  ax.h.resize(n);
+  ax.c.resize(n);
+  for (int i = 0; i < n; ++i) {
+    ax.h[i] = ax.f[i + 1] - ax.f[i];
+    ax.c[i] = 0.5 * (ax.f[i] + ax.f[i + 1]);
+  }
+  if (periodic) {
+    const double len = ax.f[n] - ax.f[0];
+    ax.dc.resize(n);
+    for (int i = 0; i < n; ++i) ax.dc[i] = ax.c[i] - (i ? ax.c[i - 1] : ax.c[n - 1] - len);
+  } else {
+    ax.dc.resize(n + 1);
+    ax.dc[0] = 0.5 * ax.h[0];
+    ax.dc[n] = 0.5 * ax.h[n - 1];
+    for (int i = 1; i < n; ++i) ax.dc[i] = ax.c[i] - ax.c[i - 1];
+  }
+  return MR_OK;
+}
+
+// Means of 1, x, x^2 over [a, b]: a row of A (Eq. 15) or A_s (Eq. 18).
+void interval_means(double a, double b, double* row) {
+  row[0] = 1.0;
+  row[1] = 0.5 * (a + b);
+  row[2] = (a * a + a * b + b * b) / 3.0;
+}
+
+// Solve the 3x3 system M y = rhs by Gaussian elimination with partial pivoting.
+bool solve3(double M[3][3], double rhs[3], double y[3]) {
+  int p[3] = {0, 1, 2};
+  double A[3][4];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) A[r][c] = M[r][c];
+    A[r][3] = rhs[r];
+  }
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (A[piv][col] == 0.0) return false;
+    if (piv != col)
+      for (int c = 0; c < 4; ++c) std::swap(A[piv][c], A[col][c]);
+    for (int r = col + 1; r < 3; ++r) {
+      const double f = A[r][col] / A[col][col];
+      for (int c = col; c < 4; ++c) A[r][c] -= f * A[col][c];
+    }
+  }
+  (void)p;
+  for (int r = 2; r >= 0; --r) {
+    double s = A[r][3];
+    for (int c = r + 1; c < 3; ++c) s -= A[r][c] * y[c];
+    y[r] = s / A[r][r];
+  }
+  return true;
+}
+
+int stencil_start(const Axis& ax, int I) {
+  if (ax.periodic) return I - 1;
+  return std::min(std::max(I - 1, 0), ax.nc - 3);
+}
+
+// R_I = A_s A^-1 for every coarse cell (local coordinate (x - centre)/H), and
+// the wrapped stencil cell indices.  m = 1 gives R = [0 1 0] on the cell itself.
+int refinement_table(const Axis& ax, vector<double>& R, vector<int>& idx, vector<int>& start) {
+  const int nc = ax.nc, m = ax.m;
+  R.assign((size_t)nc * m * 3, 0.0);
+  idx.assign((size_t)nc * 3, 0);
+  start.assign(nc, 0);
+  if (m == 1) {
+    for (int I = 0; I < nc; ++I) {
+      R[(size_t)I * 3 + 1] = 1.0;
+      for (int r = 0; r < 3; ++r) idx[I * 3 + r] = ((I - 1 + r) % nc + nc) % nc;
+      start[I] = I - 1;
+    }
+    return MR_OK;
+  }
+  if (nc < 3) return MR_EINVAL;
+  const double len = ax.f[ax.n] - ax.f[0];
+  for (int I = 0; I < nc; ++I) {
+    const double X0 = ax.f[(size_t)I * m], X1 = ax.f[(size_t)(I + 1) * m];
+    const double centre = 0.5 * (X0 + X1), H = X1 - X0;
+    const int s = stencil_start(ax, I);
+    start[I] = s;
+    double A[3][3];
+    for (int r = 0; r < 3; ++r) {
+      int cell = s + r;
+      double shift = 0.0;
+      if (ax.periodic) {
+        if (cell < 0) { cell += nc; shift = -len; }
+        if (cell >= nc) { cell -= nc; shift = len; }
+      }
+      idx[I * 3 + r] = cell;
+      const double a = (ax.f[(size_t)cell * m] + shift - centre) / H;
+      const double b = (ax.f[(size_t)(cell + 1) * m] + shift - centre) / H;
+      interval_means(a, b, A[r]);
+    }
+    // R A = A_s  <=>  A^T R^T = A_s^T : one 3x3 solve per sub-interval row
+    double At[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) At[r][c] = A[c][r];
+    for (int q = 0; q < m; ++q) {
+      const double a = (ax.f[(size_t)I * m + q] - centre) / H;
+      const double b = (ax.f[(size_t)I * m + q + 1] - centre) / H;
+      double row[3], y[3];
+      interval_means(a, b, row);
+      double Mt[3][3];
+      memcpy(Mt, At, sizeof(Mt));
+      if (!solve3(Mt, row, y)) return MR_EINVAL;
+      for (int r = 0; r < 3; ++r) R[((size_t)I * m + q) * 3 + r] = y[r];
+    }
+  }
+  return MR_OK;
+}
+
+struct Problem {
+  Axis x, y, z;
+  double kappa = 0.0;
+};
+
+int check_desc(const mr_desc* d, Problem& P) {
+  if (!d) return MR_EINVAL;
+  if (d->ncx < 1 || d->ncy < 1 || d->ncz < 1 || d->mx < 1 || d->my < 1 || d->mz < 1) return MR_EINVAL;
+  const int64_t nx = (int64_t)d->ncx * d->mx, ny = (int64_t)d->ncy * d->my, nz = (int64_t)d->ncz * d->mz;
+  if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return MR_ESHAPE;
+  if (nx * ny * (nz + 1) > (int64_t)INT32_MAX) return MR_ESHAPE;   // kernels index with int32
+  if ((d->mx > 1 && d->ncx < 3) || (d->my > 1 && d->ncy < 3) || (d->mz > 1 && d->ncz < 3)) return MR_EINVAL;
+  if (d->bc_bot != MR_DIRICHLET && d->bc_bot != MR_ADIABATIC) return MR_EINVAL;
+  if (d->bc_top != MR_DIRICHLET && d->bc_top != MR_ADIABATIC) return MR_EINVAL;
+  if (d->precision != MR_FP64 && d->precision != MR_FP32) return MR_EINVAL;
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return MR_EINVAL;
+  if (!(d->ra > 0.0) || !(d->pr > 0.0) || !std::isfinite(d->ra * d->pr)) return MR_EINVAL;
+  if (d->n_avg < 0) return MR_EINVAL;
+  if (!std::isfinite(d->t_bot) || !std::isfinite(d->t_top)) return MR_EINVAL;
+  int st;
+  if ((st = build_axis(d->xf, (int)nx, d->mx, true, P.x)) != MR_OK) return st;
+  if ((st = build_axis(d->yf, (int)ny, d->my, true, P.y)) != MR_OK) return st;
+  if ((st = build_axis(d->zf, (int)nz, d->mz, false, P.z)) != MR_OK) return st;
+  P.kappa = 1.0 / sqrt(d->ra * d->pr);
+  // explicit x/y diffusion: the leapfrog step is forward Euler over 2 dt
+  const double hxm = *std::min_element(P.x.h.begin(), P.x.h.end());
+  const double hym = *std::min_element(P.y.h.begin(), P.y.h.end());
+  const double num = 2.0 * d->dt * P.kappa * (4.0 / (hxm * hxm) + 4.0 / (hym * hym));
+  if (!(num <= 1.0)) return MR_EINVAL;
+  return MR_OK;
+}
+
+double kind_tau(int kind, double dt) {
+  return kind == mr::KIND_STARTUP ? dt : (kind == mr::KIND_AVERAGE ? 1.5 * dt : 2.0 * dt);
+}
+
+// Tridiagonal I - tk Lz (rows k: sub couples k-1, sup couples k+1) and the
+// Dirichlet wall source b_z with Lz theta = Lz0 theta + b_z.
+void z_system(const Axis& z, const mr_desc* d, double tk, double* sub, double* diag, double* sup,
+              double* bz) {
+  const int nz = z.n;
+  for (int k = 0; k < nz; ++k) {
+    const double lo = k > 0 ? -tk / (z.h[k] * z.dc[k]) : 0.0;
+    const double hi = k < nz - 1 ? -tk / (z.h[k] * z.dc[k + 1]) : 0.0;
+    if (sub) sub[k] = lo;
+    if (sup) sup[k] = hi;
+    double dg = 1.0 - lo - hi;
+    double b = 0.0;
+    if (k == 0 && d->bc_bot == MR_DIRICHLET) {
+      dg += tk / (z.h[0] * z.dc[0]);
+      b += d->t_bot / (z.h[0] * z.dc[0]);
+    }
+    if (k == nz - 1 && d->bc_top == MR_DIRICHLET) {
+      dg += tk / (z.h[nz - 1] * z.dc[nz]);
+      b += d->t_top / (z.h[nz - 1] * z.dc[nz]);
+    }
+    if (diag) diag[k] = dg;
+    if (bz) bz[k] = b;
+  }
+}
+
+// Host image of one ZSys.
+struct ZHost {
+  vector<double> m, a, cp, G, B, Fe, Gs, Bs, tkb;
+};
+
+// Thomas factors and chunk coupling vectors of the system (sub, diag, sup),
+// for chunks [c L, min((c+1) L, nz)).  With the forward sweep
+// d_k = m_k r_k + a_k d_{k-1} and back substitution x_k = d_k - cp_k x_{k+1},
+// a chunk that starts its sweeps from zero gets x_hat; the true solution is
+// x_k = x_hat_k + D G_k + X B_k with D = d at the level below the chunk and
+// X = x at the level above it.
+bool z_factors(int nz, int L, const double* sub, const double* diag, const double* sup, ZHost& z) {
+  const int nch = (nz + L - 1) / L;
+  z.m.resize(nz); z.a.resize(nz); z.cp.resize(nz); z.G.resize(nz); z.B.resize(nz);
+  z.Fe.resize(nch); z.Gs.resize(nch); z.Bs.resize(nch);
+  double cprev = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double den = diag[k] - (k ? sub[k] * cprev : 0.0);
+    if (den == 0.0 || !std::isfinite(den)) return false;
+    z.m[k] = 1.0 / den;
+    z.a[k] = k ? -sub[k] * z.m[k] : 0.0;
+    z.cp[k] = k < nz - 1 ? sup[k] * z.m[k] : 0.0;
+    cprev = z.cp[k];
+  }
+  vector<double> F(nz);
+  for (int c = 0; c < nch; ++c) {
+    const int k0 = c * L, k1 = std::min(k0 + L, nz);
+    double f = 1.0;
+    for (int k = k0; k < k1; ++k) { f *= z.a[k]; F[k] = f; }
+    double g = 0.0, b = 1.0;
+    for (int k = k1 - 1; k >= k0; --k) {
+      g = F[k] - z.cp[k] * g;
+      z.G[k] = g;
+      b *= -z.cp[k];
+      z.B[k] = b;
+    }
+    z.Fe[c] = F[k1 - 1];
+    z.Gs[c] = z.G[k0];
+    z.Bs[c] = z.B[k0];
+  }
+  return true;
+}
+
+int choose_chunks(int nz, int& L, int& nch) {
+  for (int l : mr::kChunkLens) {
+    if ((nz + l - 1) / l <= mr::kMaxChunks) {
+      L = l;
+      nch = (nz + l - 1) / l;
+      return MR_OK;
+    }
+  }
+  return MR_ESHAPE;
+}
+
+// Byte buffer that hands out 256-byte aligned slots.
+struct Packer {
+  vector<char> buf;
+  size_t put(const void* p, size_t bytes) {
+    size_t off = (buf.size() + 255) & ~(size_t)255;
+    buf.resize(off + bytes);
+    if (bytes) memcpy(buf.data() + off, p, bytes);
+    return off;
+  }
+  template <typename T>
+  size_t put(const vector<T>& v) { return put(v.data(), v.size() * sizeof(T)); }
+};
+
+template <typename T>
+vector<T> cast(const vector<double>& v) { return vector<T>(v.begin(), v.end()); }
+
+vector<double> inv(const vector<double>& v) {
+  vector<double> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = 1.0 / v[i];
+  return o;
+}
+
+struct GeomOffsets {
+  size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz;
+};
+
+template <typename T>
+GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, const vector<int>* idx) {
+  GeomOffsets o;
+  o.hx = pk.put(cast<T>(P.x.h));
+  o.ihx = pk.put(cast<T>(inv(P.x.h)));
+  o.idxc = pk.put(cast<T>(inv(P.x.dc)));
+  o.hy = pk.put(cast<T>(P.y.h));
+  o.ihy = pk.put(cast<T>(inv(P.y.h)));
+  o.idyc = pk.put(cast<T>(inv(P.y.dc)));
+  o.hz = pk.put(cast<T>(P.z.h));
+  o.ihz = pk.put(cast<T>(inv(P.z.h)));
+  vector<double> HX(P.x.nc), HY(P.y.nc);
+  for (int I = 0; I < P.x.nc; ++I) HX[I] = 1.0 / (P.x.f[(size_t)(I + 1) * P.x.m] - P.x.f[(size_t)I * P.x.m]);
+  for (int J = 0; J < P.y.nc; ++J) HY[J] = 1.0 / (P.y.f[(size_t)(J + 1) * P.y.m] - P.y.f[(size_t)J * P.y.m]);
+  o.iHX = pk.put(cast<T>(HX));
+  o.iHY = pk.put(cast<T>(HY));
+  o.Rx = pk.put(cast<T>(R[0]));
+  o.Ry = pk.put(cast<T>(R[1]));
+  o.Rz = pk.put(cast<T>(R[2]));
+  o.sx = pk.put(idx[0]);
+  o.sy = pk.put(idx[1]);
+  o.sz = pk.put(idx[2]);
+  return o;
+}
+
+template <typename T>
+mr::Geom<T> geom_ptrs(char* base, const GeomOffsets& o) {
+  mr::Geom<T> g;
+  g.hx = (const T*)(base + o.hx); g.ihx = (const T*)(base + o.ihx); g.idxc = (const T*)(base + o.idxc);
+  g.hy = (const T*)(base + o.hy); g.ihy = (const T*)(base + o.ihy); g.idyc = (const T*)(base + o.idyc);
+  g.hz = (const T*)(base + o.hz); g.ihz = (const T*)(base + o.ihz);
+  g.iHX = (const T*)(base + o.iHX); g.iHY = (const T*)(base + o.iHY);
+  g.Rx = (const T*)(base + o.Rx); g.Ry = (const T*)(base + o.Ry); g.Rz = (const T*)(base + o.Rz);
+  g.sx = (const int*)(base + o.sx); g.sy = (const int*)(base + o.sy); g.sz = (const int*)(base + o.sz);
+  return g;
+}
+
+struct ZOffsets {
+  size_t m, a, cp, G, B, Fe, Gs, Bs, tkb;
+};
+
+ZOffsets pack_z(Packer& pk, const ZHost& z) {
+  ZOffsets o;
+  o.m = pk.put(z.m); o.a = pk.put(z.a); o.cp = pk.put(z.cp); o.G = pk.put(z.G); o.B = pk.put(z.B);
+  o.Fe = pk.put(z.Fe); o.Gs = pk.put(z.Gs); o.Bs = pk.put(z.Bs); o.tkb = pk.put(z.tkb);
+  return o;
+}
+
+mr::ZSys z_ptrs(char* base, const ZOffsets& o) {
+  mr::ZSys z;
+  z.m = (const double*)(base + o.m); z.a = (const double*)(base + o.a); z.cp = (const double*)(base + o.cp);
+  z.G = (const double*)(base + o.G); z.B = (const double*)(base + o.B);
+  z.Fe = (const double*)(base + o.Fe); z.Gs = (const double*)(base + o.Gs); z.Bs = (const double*)(base + o.Bs);
+  z.tkb = (const double*)(base + o.tkb);
+  return z;
+}
+
+int hip_fail(mr_ctx* c, hipError_t e) {
+  if (c) c->last_err = (int)e;
+  (void)hipGetLastError();
+  return MR_EHIP;
+}
+
+inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+size_t elem_size(const mr_ctx* c) { return c->precision == MR_FP64 ? 8 : 4; }
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char* mr_status_string(int status) {
+  switch (status) {
+    case MR_OK: return "ok";
+    case MR_EINVAL: return "invalid argument";
+    case MR_ESHAPE: return "unsupported size";
+    case MR_EHIP: return "HIP runtime error";
+    case MR_ENOMEM: return "out of device memory";
+    case MR_ENONFINITE: return "non-finite value in reduction";
+    default: return "unknown status";
+  }
+}
+
+int mr_last_hip_error(const mr_ctx* ctx) { return ctx ? ctx->last_err : 0; }
+
+int mr_get_dims(const mr_ctx* ctx, int32_t* nx, int32_t* ny, int32_t* nz, int32_t* precision) {
+  if (!ctx) return MR_EINVAL;
+  if (nx) *nx = ctx->nx;
+  if (ny) *ny = ctx->ny;
+  if (nz) *nz = ctx->nz;
+  if (precision) *precision = ctx->precision;
+  return MR_OK;
+}
+
+int mr_host_refinement_table(const mr_desc* desc, int32_t axis, double* R_out, int32_t* start_out) {
+  Problem P;
+  int st = check_desc(desc, P);
+  if (st != MR_OK) return st;
+  if (axis < 0 || axis > 2) return MR_EINVAL;
+  const Axis& ax = axis == 0 ? P.x : (axis == 1 ? P.y : P.z);
+  vector<double> R;
+  vector<int> idx, start;
+  if ((st = refinement_table(ax, R, idx, start)) != MR_OK) return st;
+  if (R_out) memcpy(R_out, R.data(), R.size() * sizeof(double));
+  if (start_out)
+    for (int I = 0; I < ax.nc; ++I) start_out[I] = start[I];
+  return MR_OK;
+}
+
+int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, double* sup,
+                     double* bz, double* tau_out) {
+  Problem P;
+  int st = check_desc(desc, P);
+  if (st != MR_OK) return st;
+  if (n < 0) return MR_EINVAL;
+  const double tau = kind_tau(mr::step_kind(n, desc->n_avg), desc->dt);
+  z_system(P.z, desc, tau * P.kappa, sub, diag, sup, bz);
+  if (tau_out) *tau_out = tau;
+  return MR_OK;
+}
+
+int mr_init(const mr_desc* desc, mr_ctx** out) {
+  if (!out) return MR_EINVAL;
+  Problem P;
+  int st = check_desc(desc, P);
+  if (st != MR_OK) return st;
+  int L = 0, nch = 0;
+  if ((st = choose_chunks(P.z.n, L, nch)) != MR_OK) return st;
+
+  vector<double> R[3];
+  vector<int> idx[3], start[3];
+  const Axis* axes[3] = {&P.x, &P.y, &P.z};
+  for (int a = 0; a < 3; ++a)
+    if ((st = refinement_table(*axes[a], R[a], idx[a], start[a])) != MR_OK) return st;
+
+  Packer pk;
+  GeomOffsets o64 = pack_geom<double>(pk, P, R, idx);
+  GeomOffsets o32 = pack_geom<float>(pk, P, R, idx);
+  ZOffsets zfo[mr::NKINDS], zto[mr::NKINDS];
+  double taus[mr::NKINDS];
+  const int nz = P.z.n;
+  vector<double> sub(nz), diag(nz), sup(nz), bz(nz), tsub(nz), tsup(nz);
+  for (int kind = 0; kind < mr::NKINDS; ++kind) {
+    const double tau = kind_tau(kind, desc->dt);
+    taus[kind] = tau;
+    const double tk = tau * P.kappa;
+    z_system(P.z, desc, tk, sub.data(), diag.data(), sup.data(), bz.data());
+    ZHost zh, th;
+    if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
+    zh.tkb.resize(nz);
+    for (int k = 0; k < nz; ++k) zh.tkb[k] = tk * bz[k];
+    // transpose: sub^T_k = sup_{k-1}, sup^T_k = sub_{k+1}
+    for (int k = 0; k < nz; ++k) {
+      tsub[k] = k > 0 ? sup[k - 1] : 0.0;
+      tsup[k] = k < nz - 1 ? sub[k + 1] : 0.0;
+    }
+    if (!z_factors(nz, L, tsub.data(), diag.data(), tsup.data(), th)) return MR_EINVAL;
+    th.tkb.assign(nz, 0.0);
+    zfo[kind] = pack_z(pk, zh);
+    zto[kind] = pack_z(pk, th);
+  }
+  vector<double> dcz(P.z.dc);
+  size_t o_hx64 = pk.put(P.x.h), o_hy64 = pk.put(P.y.h), o_dcz = pk.put(dcz), o_hz64 = pk.put(P.z.h);
+
+  mr_ctx* c = new (std::nothrow) mr_ctx();
+  if (!c) return MR_ENOMEM;
+  memset((void*)c, 0, sizeof(mr_ctx));
+  c->nx = P.x.n; c->ny = P.y.n; c->nz = P.z.n;
+  c->ncx = P.x.nc; c->ncy = P.y.nc; c->ncz = P.z.nc;
+  c->mx = desc->mx; c->my = desc->my; c->mz = desc->mz;
+  c->precision = desc->precision;
+  c->kappa = P.kappa; c->dt = desc->dt; c->ra = desc->ra; c->pr = desc->pr;
+  c->t_bot = desc->t_bot; c->t_top = desc->t_top;
+  c->bc_bot = desc->bc_bot; c->bc_top = desc->bc_top; c->n_avg = desc->n_avg;
+  c->L = L; c->nch = nch;
+  for (int k = 0; k < mr::NKINDS; ++k) c->tau[k] = taus[k];
+  {
+    // total horizontal area, compensated
+    double s = 0.0, comp = 0.0;
+    for (int j = 0; j < P.y.n; ++j)
+      for (int i = 0; i < P.x.n; ++i) {
+        const double v = P.x.h[i] * P.y.h[j];
+        const double t = s + v;
+        comp += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+      }
+    c->atot = s + comp;
+  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { int r = hip_fail(c, e); delete c; return r; }
+  e = hipMalloc(&c->tables, pk.buf.size());
+  if (e != hipSuccess) { delete c; (void)hipGetLastError(); return MR_ENOMEM; }
+  e = hipMemcpy(c->tables, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(c->tables); int r = hip_fail(c, e); delete c; return r; }
+  char* base = (char*)c->tables;
+  c->g64 = geom_ptrs<double>(base, o64);
+  c->g32 = geom_ptrs<float>(base, o32);
+  for (int k = 0; k < mr::NKINDS; ++k) {
+    c->zf[k] = z_ptrs(base, zfo[k]);
+    c->zt[k] = z_ptrs(base, zto[k]);
+  }
+  c->hx64 = (const double*)(base + o_hx64);
+  c->areaw = (const double*)(base + o_hy64);
+  c->dcz = (const double*)(base + o_dcz);
+  c->hz64 = (const double*)(base + o_hz64);
+  *out = c;
+  return MR_OK;
+}
+
+int mr_destroy(mr_ctx* ctx) {
+  if (!ctx) return MR_OK;
+  if (ctx->tables) (void)hipFree(ctx->tables);
+  if (ctx->interp_tmp) (void)hipFree(ctx->interp_tmp);
+  if (ctx->interp_bwd_tmp) (void)hipFree(ctx->interp_bwd_tmp);
+  if (ctx->red) (void)hipFree(ctx->red);
+  delete ctx;
+  return MR_OK;
+}
+
+#define MR_LAUNCH(call)                              \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_);  \
+  } while (0)
+
+int mr_interpolate_velocity(mr_ctx* ctx, const void* U, const void* V, const void* W, void* u,
+                            void* v, void* w, void* stream) {
+  if (!ctx || !U || !V || !W || !u || !v || !w) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_refine(ctx, U, V, W, u, v, w, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_interpolate_velocity_backward(mr_ctx* ctx, const void* gu, const void* gv, const void* gw,
+                                     void* gU, void* gV, void* gW, void* stream) {
+  if (!ctx || !gu || !gv || !gw || !gU || !gV || !gW) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_refine_transpose(ctx, gu, gv, gw, gU, gV, gW, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w, double* dev_out,
+                  void* stream) {
+  if (!ctx || !u || !v || !w || !dev_out) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_divergence(ctx, u, v, w, dev_out, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_cur, void* th_next,
+                   const void* u, const void* v, const void* w, void* stream) {
+  if (!ctx || n < 0 || !th_cur || !th_next || !u || !v || !w) return MR_EINVAL;
+  if (n > 0 && !th_prev) return MR_EINVAL;
+  if (th_next == th_cur || th_next == th_prev) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_step(ctx, n, n > 0 ? th_prev : th_cur, th_cur, th_next, u, v, w,
+                            as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream) {
+  if (!ctx || n < 0 || !lam || !mu_out || lam == mu_out) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_seed(ctx, n, lam, mu_out, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const void* mu_cur,
+                            const void* lam_add, void* out, const void* u, const void* v,
+                            const void* w, void* stream) {
+  if (!ctx || n < 0 || !mu_cur || !out || !u || !v || !w) return MR_EINVAL;
+  if (out == mu_cur || (mu_next && out == mu_next) || (lam_add && out == lam_add)) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_step_backward(ctx, n, mu_next, mu_cur, lam_add, out, u, v, w,
+                                     as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps, const void* const* thetas,
+                     const void* const* mus, void* gu, void* gv, void* gw, void* stream) {
+  if (!ctx || count < 1 || count > 16 || !steps || !thetas || !mus || !gu || !gv || !gw)
+    return MR_EINVAL;
+  for (int s = 0; s < count; ++s)
+    if (steps[s] < 0 || !thetas[s] || !mus[s]) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_velocity_grad(ctx, count, steps, thetas, mus, gu, gv, gw, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile, mr_nu* host_out,
+               void* stream) {
+  if (!ctx || !theta || !w || !dev_profile) return MR_EINVAL;
+  hipStream_t s = as_stream(stream);
+  MR_LAUNCH(mr::launch_nusselt(ctx, theta, w, dev_profile, s));
+  if (host_out) {
+    double tmp[5];
+    MR_LAUNCH(hipMemcpyAsync(tmp, dev_profile + ctx->nz + 1, sizeof(tmp), hipMemcpyDeviceToHost, s));
+    MR_LAUNCH(hipStreamSynchronize(s));
+    host_out->nu_bot = tmp[0];
+    host_out->nu_top = tmp[1];
+    host_out->nu_vol = tmp[2];
+    host_out->nu_paper = tmp[3];
+    host_out->mean_theta = tmp[4];
+    for (double t : tmp)
+      if (!std::isfinite(t)) return MR_ENONFINITE;
+  }
+  return MR_OK;
+}
+
+int mr_copy_probe(const void* src, void* dst, int64_t nbytes, void* stream) {
+  if (!src || !dst || nbytes < 0 || (nbytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+    return MR_EINVAL;
+  hipError_t e = mr::launch_copy(src, dst, nbytes, as_stream(stream));
+  if (e != hipSuccess) { (void)hipGetLastError(); return MR_EHIP; }
+  return MR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations shared by the host API and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/mrscalar.h"
+
+namespace mr {
+
+// Step types of the Euler-leapfrog integrator with periodic averaging.
+enum StepKind { KIND_STARTUP = 0, KIND_LEAPFROG = 1, KIND_AVERAGE = 2, NKINDS = 3 };
+
+// Largest number of z chunks (one wavefront each) of the line solver, and the
+// chunk lengths the step kernels are instantiated for.
+constexpr int kMaxChunks = 16;
+constexpr int kChunkLens[] = {8, 16, 24, 32, 40};
+constexpr int kWave = 64;
+
+// Grid tables of one precision (device pointers into the context's table block).
+template <typename T>
+struct Geom {
+  const T* hx;    // [nx] dense widths
+  const T* ihx;   // [nx] 1/hx
+  const T* idxc;  // [nx] 1/(xc_i - xc_{i-1}) across face i (periodic)
+  const T* hy;
+  const T* ihy;
+  const T* idyc;
+  const T* hz;    // [nz]
+  const T* ihz;   // [nz]
+  const T* iHX;   // [ncx] 1/coarse width
+  const T* iHY;   // [ncy]
+  const T* Rx;    // [ncx][mx][3] refinement matrices (Eq. 19)
+  const T* Ry;    // [ncy][my][3]
+  const T* Rz;    // [ncz][mz][3]
+  const int* sx;  // [ncx][3] stencil cells (wrapped)
+  const int* sy;  // [ncy][3]
+  const int* sz;  // [ncz][3]
+};
+
+// Factors of one tridiagonal system (I - tau kappa Lz or its transpose) for
+// the chunked line solver: Thomas factors and the chunk coupling vectors.
+struct ZSys {
+  const double* m;   // [nz] 1/(diag_k - sub_k cp_{k-1})
+  const double* a;   // [nz] -sub_k m_k
+  const double* cp;  // [nz] sup_k m_k
+  const double* G;   // [nz] response of x_k to the value entering its chunk from below
+  const double* B;   // [nz] response of x_k to the value entering its chunk from above
+  const double* Fe;  // [nch] product of a over each chunk
+  const double* Gs;  // [nch] G at each chunk start
+  const double* Bs;  // [nch] B at each chunk start
+  const double* tkb; // [nz] tau kappa b_z (wall source); zeros for the transpose
+};
+
+}  // namespace mr
+
+struct mr_ctx {
+  int nx, ny, nz, ncx, ncy, ncz, mx, my, mz;
+  int precision;
+  double kappa, dt, ra, pr, t_bot, t_top;
+  int bc_bot, bc_top, n_avg;
+  int device;
+  int last_err;
+  int L, nch;                      // z chunk length and count of the line solver
+  double atot;                     // total horizontal area
+  double tau[mr::NKINDS];
+  void* tables;                    // one device block with every table
+  mr::Geom<double> g64;
+  mr::Geom<float> g32;
+  mr::ZSys zf[mr::NKINDS];         // forward systems per step kind
+  mr::ZSys zt[mr::NKINDS];         // transposed systems per step kind
+  const double* areaw;             // [ny] hy_j (area = hx_i * hy_j, built in kernel)
+  const double* hx64;              // [nx]
+  const double* dcz;               // [nz+1] centre distances across z faces (wall: half cell)
+  const double* hz64;              // [nz]
+  void* interp_tmp;                // forward refinement intermediates (lazy)
+  size_t interp_tmp_bytes;
+  void* interp_bwd_tmp;            // transposed refinement intermediates (lazy)
+  size_t interp_bwd_tmp_bytes;
+  double* red;                     // reduction partials
+  size_t red_bytes;
+};
+
+// Launchers (return hipError_t of the launch).
+namespace mr {
+hipError_t launch_refine(mr_ctx* c, const void* U, const void* V, const void* W, void* u, void* v,
+                         void* w, hipStream_t s);
+hipError_t launch_refine_transpose(mr_ctx* c, const void* gu, const void* gv, const void* gw,
+                                   void* gU, void* gV, void* gW, hipStream_t s);
+hipError_t launch_step(mr_ctx* c, int64_t n, const void* thp, const void* thc, void* thn,
+                       const void* u, const void* v, const void* w, hipStream_t s);
+hipError_t launch_seed(mr_ctx* c, int64_t n, const void* lam, void* mu, hipStream_t s);
+hipError_t launch_step_backward(mr_ctx* c, int64_t n, const void* mun, const void* muc,
+                                const void* lam_add, void* out, const void* u, const void* v,
+                                const void* w, hipStream_t s);
+hipError_t launch_velocity_grad(mr_ctx* c, int count, const int64_t* steps,
+                                const void* const* thetas, const void* const* mus, void* gu,
+                                void* gv, void* gw, hipStream_t s);
+hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void* w, double* out,
+                             hipStream_t s);
+hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, int64_t nbytes, hipStream_t s);
+
+// Step-type bookkeeping shared by the host API and the launchers.
+inline int step_kind(int64_t n, int n_avg) {
+  if (n == 0) return KIND_STARTUP;
+  if (n_avg > 0 && (n + 1) % n_avg == 0) return KIND_AVERAGE;
+  return KIND_LEAPFROG;
+}
+inline double alpha_prev(int kind) { return kind == KIND_STARTUP ? 0.0 : (kind == KIND_AVERAGE ? 0.5 : 1.0); }
+inline double alpha_cur(int kind) { return kind == KIND_STARTUP ? 1.0 : (kind == KIND_AVERAGE ? 0.5 : 0.0); }
+
+// XCD-aware tile order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs; this remaps them so that each XCD walks a contiguous range of
+// tiles (neighbouring rows share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int full = (nblocks / kXcd) * kXcd;
+  if (bid >= full) return bid;
+  const int per = full / kXcd;
+  return (bid % kXcd) * per + bid / kXcd;
+}
+}  // namespace mr

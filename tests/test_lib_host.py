@@ -1,0 +1,136 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol the header
+declares, builds the same grid tables as the oracle on the host, and rejects
+bad descriptors before touching a GPU.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_03426_amd import _lib, inputs
+from paper_1805_03426_amd.context import host_refinement_table, host_z_system, make_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mrscalar.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(mr_[a-z_0-9]+)\s*\(", text))
+    assert declared, "no declarations parsed"
+    L = _lib.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(_lib.EXPORTS)
+
+
+def test_status_strings():
+    assert _lib.status_string(0) == "ok"
+    assert "invalid" in _lib.status_string(-1)
+
+
+def _desc(nc=(6, 5, 7), m=(2, 3, 2), gamma=1.5, **kw):
+    xf = inputs.uniform_faces(nc[0] * m[0])
+    yf = inputs.uniform_faces(nc[1] * m[1])
+    zf = inputs.tanh_faces(nc[2] * m[2], gamma)
+    args = dict(ra=1e6, pr=4.38, dt=1e-3)
+    args.update(kw)
+    return make_desc(xf, yf, zf, m, **args), (xf, yf, zf)
+
+
+@pytest.mark.parametrize("m", [(2, 2, 2), (3, 2, 4), (1, 3, 1)])
+def test_host_refinement_tables_match_oracle(m):
+    (d, keep), (xf, yf, zf) = _desc(m=m, gamma=2.0)
+    g = O.Grid(xf, yf, zf, m)
+    for axis, ax in enumerate((g.x, g.y, g.z)):
+        R, s = host_refinement_table(d, axis)
+        for I in range(ax.nc):
+            np.testing.assert_allclose(R[I], O.r_matrix(ax, I), rtol=0, atol=1e-14)
+            if ax.m > 1:
+                assert s[I] == O.stencil_start(ax, I)
+
+
+def test_host_refinement_stretched_x():
+    rng = np.random.default_rng(3)
+    hx = rng.uniform(0.5, 2.0, 12)
+    xf = np.concatenate([[0], np.cumsum(hx)]) / hx.sum()
+    yf = inputs.uniform_faces(8)
+    zf = inputs.tanh_faces(12, 1.0)
+    d, keep = make_desc(xf, yf, zf, (3, 2, 2), ra=1e4, pr=1.0, dt=1e-4)
+    g = O.Grid(xf, yf, zf, (3, 2, 2))
+    R, _ = host_refinement_table(d, 0)
+    for I in range(4):
+        np.testing.assert_allclose(R[I], O.r_matrix(g.x, I), atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", [("dirichlet", "dirichlet"), ("adiabatic", "dirichlet"),
+                                ("dirichlet", "adiabatic")])
+def test_host_z_system_matches_oracle(bc):
+    (d, keep), (xf, yf, zf) = _desc(gamma=2.5, n_avg=4, bc_bot=bc[0], bc_top=bc[1], t_bot=0.8, t_top=0.1)
+    g = O.Grid(xf, yf, zf, (2, 3, 2))
+    p = O.ScalarParams.from_ra_pr(1e6, 4.38, dt=1e-3, n_avg=4, bc_bot=bc[0], bc_top=bc[1], t_bot=0.8,
+                                  t_top=0.1)
+    for n in (0, 1, 3, 7):
+        sub, diag, sup, bz, tau = host_z_system(d, n)
+        want_tau = O.step_kind(n, 4, 1e-3)[0]
+        assert tau == want_tau
+        osub, odiag, osup, obz = O.z_matrix(g, tau * p.kappa, p)
+        np.testing.assert_allclose(sub, osub, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(diag, odiag, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(sup, osup, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(bz, obz, rtol=1e-14, atol=0)
+
+
+def _init_status(**over):
+    """mr_init status for a descriptor with one field changed (checked on the
+    host before any HIP call)."""
+    (d, keep), _ = _desc()
+    for k, v in over.items():
+        setattr(d, k, v)
+    ctx = ctypes.c_void_p()
+    return _lib.lib().mr_init(ctypes.byref(d), ctypes.byref(ctx))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("mx", 0), ("ncz", 0), ("ncx", 2), ("dt", 0.0), ("dt", -1.0), ("ra", 0.0), ("pr", -2.0),
+    ("bc_bot", 7), ("precision", 5), ("n_avg", -1), ("dt", float("nan")),
+])
+def test_init_rejects_bad_descriptor(field, value):
+    assert _init_status(**{field: value}) == _lib.MR_EINVAL
+
+
+def test_init_rejects_non_monotone_faces():
+    (d, keep), (xf, yf, zf) = _desc()
+    zbad = zf.copy()
+    zbad[3], zbad[4] = zbad[4], zbad[3]
+    d2, keep2 = make_desc(xf, yf, zbad, (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3)
+    ctx = ctypes.c_void_p()
+    assert _lib.lib().mr_init(ctypes.byref(d2), ctypes.byref(ctx)) == _lib.MR_EINVAL
+    assert not ctx.value
+
+
+def test_init_rejects_large_diffusion_number():
+    """2 dt kappa (4/hx^2 + 4/hy^2) > 1 is refused (explicit x/y diffusion)."""
+    xf = inputs.uniform_faces(64)
+    d, keep = make_desc(xf, xf, inputs.uniform_faces(8), (2, 2, 2), ra=1.0, pr=1.0, dt=1e-3)
+    ctx = ctypes.c_void_p()
+    assert _lib.lib().mr_init(ctypes.byref(d), ctypes.byref(ctx)) == _lib.MR_EINVAL
+
+
+def test_init_rejects_too_many_z_levels():
+    """More z levels than the line solver's 16 chunks x 40 levels is MR_ESHAPE."""
+    xf = inputs.uniform_faces(8)
+    d, keep = make_desc(xf, xf, inputs.uniform_faces(642), (2, 2, 2), ra=1e6, pr=1.0, dt=1e-5)
+    ctx = ctypes.c_void_p()
+    assert _lib.lib().mr_init(ctypes.byref(d), ctypes.byref(ctx)) == _lib.MR_ESHAPE
+
+
+def test_null_arguments_rejected():
+    L = _lib.lib()
+    assert L.mr_init(None, None) == _lib.MR_EINVAL
+    assert L.mr_destroy(None) == _lib.MR_OK
+    assert L.mr_scalar_step(None, 0, None, None, None, None, None, None, None) == _lib.MR_EINVAL
+    assert L.mr_nusselt(None, None, None, None, None, None) == _lib.MR_EINVAL
+    assert L.mr_copy_probe(None, None, 16, None) == _lib.MR_EINVAL
