@@ -1,0 +1,290 @@
+"""Benchmark of the multiple-resolution dense-grid scalar step on one MI355X.
+
+One benchmark step is one whole run of the FP64 workload rb256-m2-fp64
+(coarse 128^3 -> dense 256^3, tanh z grid, Ra 1e8, Pr 4.38): refine the
+coarse velocity, check its divergence, then 100 scalar steps with the Nusselt
+profile every 10 steps.  Inputs are resident in HBM before the timed region.
+value = dense-cell updates per second over the whole job.
+
+Also reported, outside the timed region: the same workload with FP32 storage,
+the adjoint workload (FP32, 20 steps, checkpoint every 5: forward and backward
+times), the copy-kernel bandwidth, the roofline of the dominant kernel (the
+fused scalar step) and the oracle's CPU time on a bounded sample.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1805_03426_amd import inputs  # noqa: E402
+from paper_1805_03426_amd.configs import WORKLOADS  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "dense-cell updates/s per scalar step, % HBM peak; FP32 vs FP64; adjoint/fwd"
+WORKLOAD = "rb256-m2-fp64"
+ADJOINT_WORKLOAD = "rb256-m2-adjoint-fp32"
+STEP_KERNEL = "line_kernel"
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "scalar_step_rb256_fp64_traffic.md")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources, to tell whether committed counters are stale."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1805_03426_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """Measured HBM bytes per launch of the step kernel from the committed
+    rocprofv3 counter summary, or None if absent or taken on other sources."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    text = open(PROFILE_TRAFFIC).read()
+    m_hash = re.search(r"source hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"bytes per launch \(scaled\):\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+class Run:
+    """Device-resident inputs and buffers of one workload run."""
+
+    def __init__(self, w, precision):
+        from paper_1805_03426_amd.context import Context
+        d = inputs.workload_inputs(w)
+        self.w = w
+        self.dt = d["dt"]
+        self.ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg,
+                           precision=precision)
+        dt_ = self.ctx.dtype
+        self.U, self.V, self.W = (torch.from_numpy(d[k]).to("cuda", dt_) for k in ("U", "V", "W"))
+        self.th0 = torch.from_numpy(d["theta0"]).to("cuda", dt_)
+        c = self.ctx
+        self.u, self.v, self.w_ = c.empty(c.shape_cell), c.empty(c.shape_cell), c.empty(c.shape_w)
+        self.ring = [c.empty(c.shape_cell) for _ in range(3)]
+        self.div = torch.empty(2, dtype=torch.float64, device="cuda")
+        self.nprof = max(1, w.steps // max(1, w.nu_every)) if w.nu_every else 0
+        self.prof = torch.empty((max(1, self.nprof), c.nz + 6), dtype=torch.float64, device="cuda")
+        self.host_inputs = d
+
+    def run(self, events=None):
+        """One whole run; with ``events`` (a list) it records a (start, end)
+        event pair around every scalar-step launch on the current stream."""
+        c, w = self.ctx, self.w
+        c.interpolate_velocity(self.U, self.V, self.W, out=(self.u, self.v, self.w_))
+        c.divergence(self.u, self.v, self.w_, out=self.div)
+        prev = cur = self.th0
+        slot = 0
+        q = 0
+        for n in range(w.steps):
+            out = self.ring[slot]
+            slot = (slot + 1) % 3
+            if events is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            c.scalar_step(n, prev, cur, out, self.u, self.v, self.w_)
+            if events is not None:
+                e1.record()
+                events.append((e0, e1))
+            prev, cur = cur, out
+            if w.nu_every and (n + 1) % w.nu_every == 0:
+                c.nusselt(cur, self.w_, profile=self.prof[q], sync=False)
+                q += 1
+        return cur
+
+
+def time_runs(run, k, warmup, events=None):
+    for _ in range(warmup):
+        run.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        run.run(events)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_ms(events):
+    return float(np.mean([a.elapsed_time(b) for a, b in events]))
+
+
+def copy_bandwidth():
+    from paper_1805_03426_amd.context import copy_probe
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        copy_probe(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
+def adjoint_times(steps_override=None):
+    """Forward (refine + N steps) and backward (recompute + reverse steps +
+    velocity gradient + transposed refinement) of the adjoint workload."""
+    from paper_1805_03426_amd.autograd import rollout
+    w = WORKLOADS[ADJOINT_WORKLOAD]
+    r = Run(w, "fp32")
+    N = steps_override or w.steps
+    th0 = r.th0.clone().requires_grad_(True)
+    U, V, W = (t.clone().requires_grad_(True) for t in (r.U, r.V, r.W))
+    target = torch.from_numpy(inputs.theta_initial(r.host_inputs["zf"], r.ctx.nx, r.ctx.ny,
+                                                   seed=inputs.SEED_TARGET)).to("cuda", torch.float32)
+    tf, tb = [], []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = rollout(r.ctx, th0, U, V, W, N, w.ckpt_every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = out - target
+        torch.autograd.backward(out, g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep > 0:
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+        th0.grad = U.grad = V.grad = W.grad = None
+    r.ctx.close()
+    return float(np.median(tf)), float(np.median(tb)), N
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The oracle's FP64 scalar step on the same workload, a bounded sample:
+    as many whole-field steps as fit in the budget (at least one)."""
+    import oracle as O
+    d = inputs.workload_inputs(w)
+    g = O.Grid(d["xf"], d["yf"], d["zf"], w.m)
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    uvw = O.refine_velocity(g, d["U"], d["V"], d["W"])
+    prev = cur = d["theta0"]
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        nxt = O.scalar_step(g, p, n, prev, cur, *uvw)
+        prev, cur = cur, nxt
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 8:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=w.cells * n / el, unit="dense-cell updates/s", cores=1, kind="oracle",
+                sample="%d whole-field FP64 scalar steps of %s (%d cells), NumPy single-threaded, %.1f s"
+                       % (n, w.name, w.cells, el))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32 / adjoint / copy measurements")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="launch the copy kernel on 1 GiB once (counter calibration for profiles)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the scalar step is a single-GPU kernel here "
+              "(a multi-GPU y-slab decomposition is designed but not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = WORKLOADS[WORKLOAD]
+    print("bench: %s, %d steps + %d warmup" % (w.name, args.steps, args.warmup), file=sys.stderr, flush=True)
+    run = Run(w, "fp64")
+    events = []
+    el = time_runs(run, args.steps, args.warmup, events)
+    cells_per_run = w.cells * w.steps
+    value = cells_per_run * args.steps / el
+    ms_step = kernel_ms(events)
+    alg_bytes = 6 * 8 * w.cells
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    traffic = committed_traffic()
+    run.ctx.close()
+    del run
+    torch.cuda.empty_cache()
+
+    extras = {}
+    if not args.no_extras:
+        print("bench: FP32 tier", file=sys.stderr, flush=True)
+        r32 = Run(w, "fp32")
+        ev32 = []
+        el32 = time_runs(r32, max(1, args.steps), 1, ev32)
+        ms32 = kernel_ms(ev32)
+        extras["fp32"] = dict(value=cells_per_run * max(1, args.steps) / el32, unit="dense-cell updates/s",
+                              step_kernel_ms=ms32,
+                              step_hbm_frac_alg=6 * 4 * w.cells / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        r32.ctx.close()
+        del r32
+        torch.cuda.empty_cache()
+        print("bench: adjoint", file=sys.stderr, flush=True)
+        tf, tb, nad = adjoint_times()
+        extras["adjoint"] = dict(workload=ADJOINT_WORKLOAD, steps=nad, forward_s=tf, backward_s=tb,
+                                 backward_over_forward=tb / tf)
+        torch.cuda.empty_cache()
+        extras["copy_bandwidth_GBs"] = copy_bandwidth()
+
+    if args.copy_probe:
+        from paper_1805_03426_amd.context import copy_probe
+        a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        copy_probe(a, b)
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: CPU baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "dense-cell updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded divergence-free velocity, conduction profile + noise)",
+        "config": {"workload": w.name, "coarse": list(w.nc), "dense": list(w.n), "refinement": list(w.m),
+                   "z_tanh": w.gamma, "ra": w.ra, "pr": w.pr, "scalar_steps_per_run": w.steps,
+                   "nusselt_every": w.nu_every, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_kernel_ms": ms_step,
+                     "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    line.update(extras)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

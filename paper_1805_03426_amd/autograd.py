@@ -1,0 +1,86 @@
+"""Differentiable rollout: theta^N = S_{N-1} o ... o S_0 (theta^0; P(U, V, W)).
+
+``ScalarRollout`` is a torch.autograd.Function whose forward refines the
+coarse velocity once (it is frozen over the rollout), runs N scalar steps on a
+ring of three buffers and keeps the pair (theta^{n-1}, theta^n) every K steps.
+Its backward walks the checkpoint segments in reverse: it recomputes the
+states of a segment from its checkpoint, runs the fused reverse step of each
+step (transposed implicit solve fused with the transposed stencils), adds the
+segment's dense face-velocity gradient once from the stored (theta^n, mu^n)
+pairs, and finally maps the dense face gradient to the coarse faces with the
+transposed refinement.  Every step of the computation is a library call.
+"""
+import torch
+
+MAX_GRAD_STEPS = 16
+
+
+class ScalarRollout(torch.autograd.Function):
+
+    @staticmethod
+    def forward(fctx, mr, nsteps, ckpt_every, theta0, U, V, W):
+        if nsteps < 1:
+            raise ValueError("nsteps must be >= 1")
+        K = max(1, min(int(ckpt_every), MAX_GRAD_STEPS))
+        u, v, w = mr.interpolate_velocity(U.detach(), V.detach(), W.detach())
+        ring = [theta0.detach(), mr.empty(mr.shape_cell), mr.empty(mr.shape_cell), mr.empty(mr.shape_cell)]
+        prev = cur = ring[0]
+        ckpts = {}
+        slot = 1
+        for n in range(nsteps):
+            if n % K == 0:
+                ckpts[n] = (None if n == 0 else prev.clone(), cur.clone())
+            out = ring[slot]
+            slot = 1 + (slot % 3)
+            mr.scalar_step(n, prev, cur, out, u, v, w)
+            prev, cur = cur, out
+        fctx.mr = mr
+        fctx.nsteps = nsteps
+        fctx.K = K
+        fctx.ckpts = ckpts
+        fctx.uvw = (u, v, w)
+        return cur.clone()
+
+    @staticmethod
+    def backward(fctx, g_out):
+        mr, N, K = fctx.mr, fctx.nsteps, fctx.K
+        u, v, w = fctx.uvw
+        g_out = g_out.contiguous()
+        gu = torch.zeros_like(u)
+        gv = torch.zeros_like(v)
+        gw = torch.zeros_like(w)
+        mu_next = None
+        mu_cur = mr.empty(mr.shape_cell)
+        mr.adjoint_seed(N - 1, g_out, mu_cur)
+        g_theta0 = None
+        for s in reversed(range(0, N, K)):
+            e = min(s + K, N)
+            # recompute theta^s .. theta^{e-1}
+            pprev, pcur = fctx.ckpts[s]
+            states = {s: pcur}
+            prev = pprev if pprev is not None else pcur
+            cur = pcur
+            for n in range(s, e - 1):
+                out = mr.empty(mr.shape_cell)
+                mr.scalar_step(n, prev, cur, out, u, v, w)
+                states[n + 1] = out
+                prev, cur = cur, out
+            # reverse steps e-1 .. s; mu^n is kept for the velocity gradient
+            mus = {}
+            for n in range(e - 1, s - 1, -1):
+                mus[n] = mu_cur
+                out = mr.empty(mr.shape_cell)
+                mr.scalar_step_backward(n, mu_next, mu_cur, None, out, u, v, w)
+                if n == 0:
+                    g_theta0 = out
+                mu_next, mu_cur = mu_cur, out
+            idx = list(range(s, e))
+            mr.velocity_grad(idx, [states[n] for n in idx], [mus[n] for n in idx], gu, gv, gw)
+            del states, mus
+        gU, gV, gW = mr.interpolate_velocity_backward(gu, gv, gw)
+        return None, None, None, g_theta0, gU, gV, gW
+
+
+def rollout(mr, theta0, U, V, W, nsteps, ckpt_every=10):
+    """theta^nsteps as a differentiable function of (theta0, U, V, W)."""
+    return ScalarRollout.apply(mr, nsteps, ckpt_every, theta0, U, V, W)

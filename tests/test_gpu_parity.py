@@ -129,7 +129,7 @@ def test_refine_random_field_closure():
     reports the oracle's maximum."""
     print("case refine random", flush=True)
     rng = np.random.default_rng(5)
-    case = Case((6, 5, 6), (2, 2, 3), 1.2)
+    case = Case((6, 5, 6), (2, 2, 3), 1.2, kmax=1)
     U = rng.standard_normal(case.U.shape)
     V = rng.standard_normal(case.V.shape)
     W = rng.standard_normal(case.W.shape)
@@ -177,7 +177,7 @@ def test_step_parity_rb64(c1):
 def test_step_parity_averaging_and_adiabatic():
     """N_p = 3 exercises the averaging step; adiabatic top wall."""
     print("case step averaging", flush=True)
-    case = Case((8, 6, 10), (2, 2, 2), 2.0, n_avg=3, bc=("dirichlet", "adiabatic"))
+    case = Case((8, 6, 10), (2, 2, 2), 2.0, kmax=2, n_avg=3, bc=("dirichlet", "adiabatic"))
     _step_parity(case, 8, FP64_TOL)
 
 
@@ -200,7 +200,7 @@ def test_step_fp32_tier_rb64(c1):
 def test_step_conduction_fixed_point_gpu():
     """u = 0 and theta = 1 - z_c: the GPU step keeps it to rounding."""
     print("case conduction", flush=True)
-    case = Case((4, 4, 32), (2, 2, 2), 2.0)
+    case = Case((4, 4, 32), (2, 2, 2), 2.0, random_velocity=True)
     th = np.broadcast_to((1.0 - case.g.z.c)[:, None, None], case.g.shape).copy()
     z = np.zeros(case.g.shape)
     zw = np.zeros((case.g.z.n + 1,) + case.g.shape[1:])
@@ -249,7 +249,7 @@ def test_nusselt_parity(c1, precision):
 
 def test_nusselt_conduction_gpu():
     print("case nusselt conduction", flush=True)
-    case = Case((4, 5, 40), (2, 2, 2), 2.5)
+    case = Case((4, 5, 40), (2, 2, 2), 2.5, random_velocity=True)
     th = np.broadcast_to((1.0 - case.g.z.c)[:, None, None], case.g.shape).copy()
     w = np.zeros((case.g.z.n + 1,) + case.g.shape[1:])
     with case.ctx() as ctx:
