@@ -26,8 +26,8 @@ enum Mode { FWD = 0, BWD = 1, BWD0 = 2, SEED = 3 };
 template <typename T>
 struct LineArgs {
   const T* a0;   // FWD: theta^{n-1} (lag);  BWD/BWD0: mu^n;          SEED: lambda
-  const T* a1;   // FWD: theta^n;           BWD/BWD0: mu^{n+1} or 0
-  const T* a2;   // BWD/BWD0: lam_add or 0
+  const T* a1;   // FWD: theta^n;           BWD/BWD0: mu^{n+1} (mu^n when absent)
+  const T* a2;   // BWD/BWD0: lam_add (mu^n when absent)
   const T* u;
   const T* v;
   const T* w;
@@ -35,17 +35,44 @@ struct LineArgs {
   Geom<T> g;
   ZSys z;        // system solved for the output (FWD: step n; BWD: transpose of step n-1)
   T ap, ac, tau, tk;   // FWD: step n;  BWD: a_c(n), tau_n, tau_n kappa (ap unused)
-  T ap1, tk1;          // BWD: a_p(n+1), tau_{n+1} kappa
+  T ap1, tk1;          // BWD: a_p(n+1), tau_{n+1} kappa (0 when there is no step n+1)
+  T s2;                // BWD: 1 with lam_add, 0 without
   int nx, ny, nz, nch;
 };
 
+#ifndef MR_STEP_PREFETCH
+#define MR_STEP_PREFETCH 1
+#endif
+#ifndef MR_STEP_MIN_BLOCKS
+#define MR_STEP_MIN_BLOCKS 1
+#endif
+// Issue the loads of level k+1 before the arithmetic of level k.
+constexpr bool kPrefetch = MR_STEP_PREFETCH != 0;
+
+// Values one z level of the stencil reads.
 template <typename T>
-__device__ __forceinline__ T ld(const T* p, int idx) {
-  return p[idx];
+struct Lvl {
+  T zp, w1;                 // z-stencil field one level up; w on the face above
+  T xm, xp, ym, yp;         // x/y neighbours of the z-stencil field
+  T u0, u1, v0, v1;         // u on faces i, i+1; v on faces j, j+1
+  T pc, pxm, pxp, pym, pyp; // second field (theta^{n-1} or mu^{n+1}) and its x/y neighbours
+  T q;                      // lam_add (reverse step)
+};
+
+// Load from a wave-uniform base at a 32-bit byte offset (scalar base + vector
+// offset addressing).
+template <typename T>
+__device__ __forceinline__ T ldb(const T* base, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+template <typename T>
+__device__ __forceinline__ void stb(T* base, unsigned boff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
 template <typename T, int L, int MODE>
-__global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
+__global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs<T> A) {
   __shared__ double sh[4][kMaxChunks][kWave];
   const int lane = threadIdx.x;
   const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -62,7 +89,11 @@ __global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
   const int jp = j == ny - 1 ? 0 : j + 1;
   const int nxy = nx * ny;
   const int k0 = c * L;
-  const int k1 = min(k0 + L, nz);
+  // offsets of the stencil points inside one z level; a level's base pointer
+  // is wave-uniform, so every load is scalar base + 32-bit lane offset
+  constexpr unsigned sz = sizeof(T);
+  const unsigned oc = (j * nx + i) * sz, oxm = (j * nx + im) * sz, oxp = (j * nx + ip) * sz;
+  const unsigned oym = (jm * nx + i) * sz, oyp = (jp * nx + i) * sz;
   const Geom<T>& g = A.g;
 
   const T ihx = g.ihx[i], ihxm = g.ihx[im], ihxp = g.ihx[ip];
@@ -73,86 +104,95 @@ __global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
 
   double d[L];
   double dprev = 0.0;
-  // z ring of the field whose z neighbours the stencil needs (theta^n or mu^n)
-  T zm = T(0), zc = T(0), zp = T(0), w0 = T(0), w1 = T(0);
+  // field whose z neighbours the stencil needs (theta^n or mu^n), carried up the chunk
+  const T* f = MODE == FWD ? A.a1 : A.a0;
+  // second stencil field: theta^{n-1} (FWD) or mu^{n+1} (BWD, a0 with zero weights if absent)
+  const T* p = MODE == FWD ? A.a0 : A.a1;
+  T zm = T(0), zc = T(0), w0 = T(0);
   if (MODE != SEED) {
-    const T* f = MODE == FWD ? A.a1 : A.a0;
-    zc = ld(f, k0 * nxy + j * nx + i);
-    if (k0 > 0) zm = ld(f, (k0 - 1) * nxy + j * nx + i);
-    w0 = ld(A.w, k0 * nxy + j * nx + i);
+    zc = ldb(f + k0 * nxy, oc);
+    zm = ldb(f + max(k0 - 1, 0) * nxy, oc);
+    w0 = ldb(A.w + k0 * nxy, oc);
   }
 
+  // All loads of one z level.  Rows k >= nz (padding of the last chunk) read
+  // the top level; their values never reach a real row (decoupled identity rows).
+  auto fetch = [&](int k) {
+    Lvl<T> v;
+    const int kc = min(k, nz - 1);
+    if (MODE == SEED) {
+      v.pc = ldb(A.a0 + kc * nxy, oc);
+      return v;
+    }
+    const T* fk = f + kc * nxy;
+    const T* uk = A.u + kc * nxy;
+    const T* vk = A.v + kc * nxy;
+    const T* pk = p + kc * nxy;
+    v.zp = ldb(f + min(k + 1, nz - 1) * nxy, oc);
+    v.w1 = ldb(A.w + (kc + 1) * nxy, oc);
+    v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp); v.ym = ldb(fk, oym); v.yp = ldb(fk, oyp);
+    v.u0 = ldb(uk, oc); v.u1 = ldb(uk, oxp);
+    v.v0 = ldb(vk, oc); v.v1 = ldb(vk, oyp);
+    v.pc = ldb(pk, oc); v.pxm = ldb(pk, oxm); v.pxp = ldb(pk, oxp);
+    v.pym = ldb(pk, oym); v.pyp = ldb(pk, oyp);
+    if (MODE != FWD) v.q = ldb(A.a2 + kc * nxy, oc);
+    return v;
+  };
+
+  Lvl<T> cur = fetch(k0);
 #pragma unroll
   for (int kk = 0; kk < L; ++kk) {
     const int k = k0 + kk;
-    if (k < k1) {
-      const int row = k * nxy + j * nx;
-      const int rm = k * nxy + jm * nx;
-      const int rp = k * nxy + jp * nx;
-      T r;
-      if (MODE == SEED) {
-        r = ld(A.a0, row + i);
+    const int kc = min(k, nz - 1);
+    Lvl<T> nxt;
+    if (kPrefetch && kk + 1 < L) nxt = fetch(k + 1);   // next level's loads in flight
+    T r;
+    if (MODE == SEED) {
+      r = cur.pc;
+    } else {
+      const T zp = cur.zp, w1 = cur.w1;
+      const T ihz = g.ihz[kc];
+      const T mlo = g.zlo[k], mhi = g.zhi[k];
+      if (MODE == FWD) {
+        // central-flux advection of theta^n (face value = mean of the two cells)
+        const T fzl = mlo * w0 * (zm + zc);
+        const T fzr = mhi * w1 * (zc + zp);
+        const T adv = -half * ((cur.u1 * (zc + cur.xp) - cur.u0 * (cur.xm + zc)) * ihx +
+                               (cur.v1 * (zc + cur.yp) - cur.v0 * (cur.ym + zc)) * ihy + (fzr - fzl) * ihz);
+        // lagged x/y diffusion of theta^{n-1}
+        const T lap = ((cur.pxp - cur.pc) * idx1 - (cur.pc - cur.pxm) * idx0) * ihx +
+                      ((cur.pyp - cur.pc) * idy1 - (cur.pc - cur.pym) * idy0) * ihy;
+        r = A.ap * cur.pc + A.ac * zc + A.tau * adv + A.tk * lap;
       } else {
-        const T* f = MODE == FWD ? A.a1 : A.a0;
-        zp = k + 1 < nz ? ld(f, row + nxy + i) : T(0);
-        w1 = ld(A.w, row + nxy + i);
-        const T fxm = ld(f, row + im), fxp = ld(f, row + ip);
-        const T fym = ld(f, rm + i), fyp = ld(f, rp + i);
-        const T u0 = ld(A.u, row + i), u1 = ld(A.u, row + ip);
-        const T v0 = ld(A.v, row + i), v1 = ld(A.v, rp + i);
-        const T ihz = g.ihz[k];
-        if (MODE == FWD) {
-          // central-flux advection of theta^n (face value = mean of the two cells)
-          const T fzl = k > 0 ? w0 * (zm + zc) : T(0);
-          const T fzr = k < nz - 1 ? w1 * (zc + zp) : T(0);
-          const T adv = -half * ((u1 * (zc + fxp) - u0 * (fxm + zc)) * ihx +
-                                 (v1 * (zc + fyp) - v0 * (fym + zc)) * ihy + (fzr - fzl) * ihz);
-          // lagged x/y diffusion of theta^{n-1}
-          const T pc = ld(A.a0, row + i);
-          const T pxm = ld(A.a0, row + im), pxp = ld(A.a0, row + ip);
-          const T pym = ld(A.a0, rm + i), pyp = ld(A.a0, rp + i);
-          const T lap = ((pxp - pc) * idx1 - (pc - pxm) * idx0) * ihx +
-                        ((pyp - pc) * idy1 - (pc - pym) * idy0) * ihy;
-          r = A.ap * pc + A.ac * zc + A.tau * adv + A.tk * lap;
-        } else {
-          // C_u^T mu^n: each face f (cells L, R) adds u_f (mu_R/h_R - mu_L/h_L)/2 to both cells
-          const T qc_x = zc * ihx, qc_y = zc * ihy, qc_z = zc * ihz;
-          T cz = T(0);
-          if (k > 0) cz += w0 * (qc_z - zm * g.ihz[k - 1]);
-          if (k < nz - 1) cz += w1 * (zp * g.ihz[k + 1] - qc_z);
-          const T cu = half * (u0 * (qc_x - fxm * ihxm) + u1 * (fxp * ihxp - qc_x) +
-                               v0 * (qc_y - fym * ihym) + v1 * (fyp * ihyp - qc_y) + cz);
-          r = A.ac * zc + A.tau * cu;
-          if (A.a1) {
-            // contribution of step n+1 through theta^n as its lagged level
-            const T nc = ld(A.a1, row + i);
-            const T nxm = ld(A.a1, row + im), nxp = ld(A.a1, row + ip);
-            const T nym = ld(A.a1, rm + i), nyp = ld(A.a1, rp + i);
-            const T qx = nc * ihx, qy = nc * ihy;
-            const T lt = ((nxm * ihxm - qx) * idx0 - (qx - nxp * ihxp) * idx1) +
-                         ((nym * ihym - qy) * idy0 - (qy - nyp * ihyp) * idy1);
-            r += A.ap1 * nc + A.tk1 * lt;
-          }
-          if (A.a2) r += ld(A.a2, row + i);
-          if (MODE == BWD0) {
-            // the start-up step also reads theta^0 for its diffusion
-            const T lt = ((fxm * ihxm - qc_x) * idx0 - (qc_x - fxp * ihxp) * idx1) +
-                         ((fym * ihym - qc_y) * idy0 - (qc_y - fyp * ihyp) * idy1);
-            r += A.tk * lt;
-          }
+        // C_u^T mu^n: each face f (cells L, R) adds u_f (mu_R/h_R - mu_L/h_L)/2 to both cells
+        const T qc_x = zc * ihx, qc_y = zc * ihy, qc_z = zc * ihz;
+        const T czl = mlo * w0 * (qc_z - zm * g.ihz[max(kc - 1, 0)]);
+        const T czr = mhi * w1 * (zp * g.ihz[min(kc + 1, nz - 1)] - qc_z);
+        const T cu = half * (cur.u0 * (qc_x - cur.xm * ihxm) + cur.u1 * (cur.xp * ihxp - qc_x) +
+                             cur.v0 * (qc_y - cur.ym * ihym) + cur.v1 * (cur.yp * ihyp - qc_y) + czl + czr);
+        // contribution of step n+1 through theta^n as its lagged level
+        const T qx = cur.pc * ihx, qy = cur.pc * ihy;
+        const T lt = ((cur.pxm * ihxm - qx) * idx0 - (qx - cur.pxp * ihxp) * idx1) +
+                     ((cur.pym * ihym - qy) * idy0 - (qy - cur.pyp * ihyp) * idy1);
+        r = A.ac * zc + A.tau * cu + A.ap1 * cur.pc + A.tk1 * lt + A.s2 * cur.q;
+        if (MODE == BWD0) {
+          // the start-up step also reads theta^0 for its diffusion
+          const T l0 = ((cur.xm * ihxm - qc_x) * idx0 - (qc_x - cur.xp * ihxp) * idx1) +
+                       ((cur.ym * ihym - qc_y) * idy0 - (qc_y - cur.yp * ihyp) * idy1);
+          r += A.tk * l0;
         }
-        zm = zc;
-        zc = zp;
-        w0 = w1;
       }
-      if (MODE == BWD0) {
-        if (act) A.out[row + i] = r;
-      } else {
-        const double rd = (double)r + A.z.tkb[k];
-        dprev = A.z.m[k] * rd + A.z.a[k] * dprev;
-        d[kk] = dprev;
-      }
+      zm = zc;
+      zc = zp;
+      w0 = w1;
     }
+    if (MODE == BWD0) {
+      if (act && k < nz) stb(A.out + k * nxy, oc, r);
+    } else {
+      dprev = A.z.m[k] * ((double)r + A.z.tkb[k]) + A.z.a[k] * dprev;
+      d[kk] = dprev;
+    }
+    if (kk + 1 < L) cur = kPrefetch ? nxt : fetch(k + 1);
   }
   if (MODE == BWD0) return;
 
@@ -160,11 +200,8 @@ __global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
   double xh = 0.0;
 #pragma unroll
   for (int kk = L - 1; kk >= 0; --kk) {
-    const int k = k0 + kk;
-    if (k < k1) {
-      xh = d[kk] - A.z.cp[k] * xh;
-      d[kk] = xh;
-    }
+    xh = d[kk] - A.z.cp[k0 + kk] * xh;
+    d[kk] = xh;
   }
   sh[0][c][lane] = dprev;  // elimination value at the top of the chunk
   sh[1][c][lane] = xh;     // local solution at the bottom of the chunk
@@ -187,10 +224,8 @@ __global__ void __launch_bounds__(1024) line_kernel(LineArgs<T> A) {
 #pragma unroll
   for (int kk = 0; kk < L; ++kk) {
     const int k = k0 + kk;
-    if (k < k1) {
-      const double x = d[kk] + D * A.z.G[k] + X * A.z.B[k];
-      if (act) A.out[k * nxy + j * nx + i] = (T)x;
-    }
+    const double x = d[kk] + D * A.z.G[k] + X * A.z.B[k];
+    if (act && k < nz) stb(A.out + k * nxy, oc, (T)x);
   }
 }
 
@@ -262,9 +297,11 @@ hipError_t bwd_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* mun, const 
                  hipStream_t s) {
   const int kind = step_kind(n, c->n_avg);
   LineArgs<T> a = base_args<T>(c, g);
+  // absent inputs are replaced by mu^n with zero weights (no branches in the kernel)
   a.a0 = (const T*)muc;
-  a.a1 = (const T*)mun;
-  a.a2 = (const T*)lam_add;
+  a.a1 = (const T*)(mun ? mun : muc);
+  a.a2 = (const T*)(lam_add ? lam_add : muc);
+  a.s2 = lam_add ? T(1) : T(0);
   a.u = (const T*)u;
   a.v = (const T*)v;
   a.w = (const T*)w;

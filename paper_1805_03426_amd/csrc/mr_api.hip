@@ -213,14 +213,16 @@ struct ZHost {
 };
 
 // Thomas factors and chunk coupling vectors of the system (sub, diag, sup),
-// for chunks [c L, min((c+1) L, nz)).  With the forward sweep
-// d_k = m_k r_k + a_k d_{k-1} and back substitution x_k = d_k - cp_k x_{k+1},
-// a chunk that starts its sweeps from zero gets x_hat; the true solution is
-// x_k = x_hat_k + D G_k + X B_k with D = d at the level below the chunk and
-// X = x at the level above it.
+// for chunks [c L, (c+1) L).  The tables are padded to nch*L rows: rows k >= nz
+// are identity rows decoupled from the system (m = 1, a = cp = 0), so every
+// chunk has exactly L rows.  With the forward sweep d_k = m_k r_k + a_k d_{k-1}
+// and back substitution x_k = d_k - cp_k x_{k+1}, a chunk that starts its
+// sweeps from zero gets x_hat; the true solution is x_k = x_hat_k + D G_k + X B_k
+// with D = d at the level below the chunk and X = x at the level above it.
 bool z_factors(int nz, int L, const double* sub, const double* diag, const double* sup, ZHost& z) {
   const int nch = (nz + L - 1) / L;
-  z.m.resize(nz); z.a.resize(nz); z.cp.resize(nz); z.G.resize(nz); z.B.resize(nz);
+  const int np = nch * L;
+  z.m.assign(np, 1.0); z.a.assign(np, 0.0); z.cp.assign(np, 0.0); z.G.assign(np, 0.0); z.B.assign(np, 0.0);
   z.Fe.resize(nch); z.Gs.resize(nch); z.Bs.resize(nch);
   double cprev = 0.0;
   for (int k = 0; k < nz; ++k) {
@@ -231,9 +233,9 @@ bool z_factors(int nz, int L, const double* sub, const double* diag, const doubl
     z.cp[k] = k < nz - 1 ? sup[k] * z.m[k] : 0.0;
     cprev = z.cp[k];
   }
-  vector<double> F(nz);
+  vector<double> F(np);
   for (int c = 0; c < nch; ++c) {
-    const int k0 = c * L, k1 = std::min(k0 + L, nz);
+    const int k0 = c * L, k1 = k0 + L;
     double f = 1.0;
     for (int k = k0; k < k1; ++k) { f *= z.a[k]; F[k] = f; }
     double g = 0.0, b = 1.0;
@@ -284,11 +286,12 @@ vector<double> inv(const vector<double>& v) {
 }
 
 struct GeomOffsets {
-  size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz;
+  size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz, zlo, zhi;
 };
 
 template <typename T>
-GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, const vector<int>* idx) {
+GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, const vector<int>* idx,
+                      int npad) {
   GeomOffsets o;
   o.hx = pk.put(cast<T>(P.x.h));
   o.ihx = pk.put(cast<T>(inv(P.x.h)));
@@ -309,6 +312,15 @@ GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, con
   o.sx = pk.put(idx[0]);
   o.sy = pk.put(idx[1]);
   o.sz = pk.put(idx[2]);
+  // interior-face masks of the z levels (the walls carry no advective flux),
+  // zero on the padding rows of the line solver
+  vector<double> lo(npad, 0.0), hi(npad, 0.0);
+  for (int k = 0; k < P.z.n; ++k) {
+    lo[k] = k > 0 ? 1.0 : 0.0;
+    hi[k] = k < P.z.n - 1 ? 1.0 : 0.0;
+  }
+  o.zlo = pk.put(cast<T>(lo));
+  o.zhi = pk.put(cast<T>(hi));
   return o;
 }
 
@@ -321,6 +333,7 @@ mr::Geom<T> geom_ptrs(char* base, const GeomOffsets& o) {
   g.iHX = (const T*)(base + o.iHX); g.iHY = (const T*)(base + o.iHY);
   g.Rx = (const T*)(base + o.Rx); g.Ry = (const T*)(base + o.Ry); g.Rz = (const T*)(base + o.Rz);
   g.sx = (const int*)(base + o.sx); g.sy = (const int*)(base + o.sy); g.sz = (const int*)(base + o.sz);
+  g.zlo = (const T*)(base + o.zlo); g.zhi = (const T*)(base + o.zhi);
   return g;
 }
 
@@ -424,8 +437,8 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     if ((st = refinement_table(*axes[a], R[a], idx[a], start[a])) != MR_OK) return st;
 
   Packer pk;
-  GeomOffsets o64 = pack_geom<double>(pk, P, R, idx);
-  GeomOffsets o32 = pack_geom<float>(pk, P, R, idx);
+  GeomOffsets o64 = pack_geom<double>(pk, P, R, idx, nch * L);
+  GeomOffsets o32 = pack_geom<float>(pk, P, R, idx, nch * L);
   ZOffsets zfo[mr::NKINDS], zto[mr::NKINDS];
   double taus[mr::NKINDS];
   const int nz = P.z.n;
@@ -437,7 +450,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     z_system(P.z, desc, tk, sub.data(), diag.data(), sup.data(), bz.data());
     ZHost zh, th;
     if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
-    zh.tkb.resize(nz);
+    zh.tkb.assign((size_t)nch * L, 0.0);
     for (int k = 0; k < nz; ++k) zh.tkb[k] = tk * bz[k];
     // transpose: sub^T_k = sup_{k-1}, sup^T_k = sub_{k+1}
     for (int k = 0; k < nz; ++k) {
@@ -445,7 +458,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
       tsup[k] = k < nz - 1 ? sub[k + 1] : 0.0;
     }
     if (!z_factors(nz, L, tsub.data(), diag.data(), tsup.data(), th)) return MR_EINVAL;
-    th.tkb.assign(nz, 0.0);
+    th.tkb.assign((size_t)nch * L, 0.0);
     zfo[kind] = pack_z(pk, zh);
     zto[kind] = pack_z(pk, th);
   }

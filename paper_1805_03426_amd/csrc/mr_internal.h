@@ -6,7 +6,7 @@
 
 #include <vector>
 
-#include "../../include/mrscalar.h"
+#include "mrscalar.h"
 
 namespace mr {
 
@@ -38,20 +38,23 @@ struct Geom {
   const int* sx;  // [ncx][3] stencil cells (wrapped)
   const int* sy;  // [ncy][3]
   const int* sz;  // [ncz][3]
+  const T* zlo;   // [nch*L] 1 where z level k has an interior face below (0 < k < nz), else 0
+  const T* zhi;   // [nch*L] 1 where z level k has an interior face above (k < nz-1), else 0
 };
 
 // Factors of one tridiagonal system (I - tau kappa Lz or its transpose) for
 // the chunked line solver: Thomas factors and the chunk coupling vectors.
+// Per-level tables hold nch*L rows; rows >= nz are decoupled identity rows.
 struct ZSys {
-  const double* m;   // [nz] 1/(diag_k - sub_k cp_{k-1})
-  const double* a;   // [nz] -sub_k m_k
-  const double* cp;  // [nz] sup_k m_k
-  const double* G;   // [nz] response of x_k to the value entering its chunk from below
-  const double* B;   // [nz] response of x_k to the value entering its chunk from above
+  const double* m;   // 1/(diag_k - sub_k cp_{k-1})
+  const double* a;   // -sub_k m_k
+  const double* cp;  // sup_k m_k
+  const double* G;   // response of x_k to the value entering its chunk from below
+  const double* B;   // response of x_k to the value entering its chunk from above
   const double* Fe;  // [nch] product of a over each chunk
   const double* Gs;  // [nch] G at each chunk start
   const double* Bs;  // [nch] B at each chunk start
-  const double* tkb; // [nz] tau kappa b_z (wall source); zeros for the transpose
+  const double* tkb; // tau kappa b_z (wall source); zeros for the transpose
 };
 
 }  // namespace mr
@@ -115,7 +118,11 @@ inline double alpha_cur(int kind) { return kind == KIND_STARTUP ? 1.0 : (kind ==
 // XCD-aware tile order: the hardware deals consecutive workgroups round-robin
 // to the 8 XCDs; this remaps them so that each XCD walks a contiguous range of
 // tiles (neighbouring rows share that XCD's L2).
+#ifndef MR_XCD_REMAP
+#define MR_XCD_REMAP 1
+#endif
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  if (!MR_XCD_REMAP) return bid;
   constexpr int kXcd = 8;
   const int full = (nblocks / kXcd) * kXcd;
   if (bid >= full) return bid;
