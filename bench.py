@@ -75,51 +75,57 @@ class Run:
         self.th0 = torch.from_numpy(d["theta0"]).to("cuda", dt_)
         c = self.ctx
         self.u, self.v, self.w_ = c.empty(c.shape_cell), c.empty(c.shape_cell), c.empty(c.shape_w)
-        self.ring = [c.empty(c.shape_cell) for _ in range(3)]
+        # ring[0] holds theta^0; the three others rotate
+        self.ring = [self.th0] + [c.empty(c.shape_cell) for _ in range(3)]
+        self.runner = c.step_runner(self.ring, self.u, self.v, self.w_)
         self.div = torch.empty(2, dtype=torch.float64, device="cuda")
         self.nprof = max(1, w.steps // max(1, w.nu_every)) if w.nu_every else 0
         self.prof = torch.empty((max(1, self.nprof), c.nz + 6), dtype=torch.float64, device="cuda")
         self.host_inputs = d
 
     def run(self, events=None):
-        """One whole run; with ``events`` (a list) it records a (start, end)
-        event pair around every scalar-step launch on the current stream."""
+        """One whole run; with ``events`` (a list of (start, end) event pairs,
+        one per step) it records a pair around every scalar-step launch on
+        the current stream."""
         c, w = self.ctx, self.w
         c.interpolate_velocity(self.U, self.V, self.W, out=(self.u, self.v, self.w_))
         c.divergence(self.u, self.v, self.w_, out=self.div)
-        prev = cur = self.th0
-        slot = 0
+        prev = cur = 0
         q = 0
         for n in range(w.steps):
-            out = self.ring[slot]
-            slot = (slot + 1) % 3
+            out = 1 + n % 3
             if events is not None:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-            c.scalar_step(n, prev, cur, out, self.u, self.v, self.w_)
+                events[n][0].record()
+            self.runner.step(n, prev, cur, out)
             if events is not None:
-                e1.record()
-                events.append((e0, e1))
+                events[n][1].record()
             prev, cur = cur, out
             if w.nu_every and (n + 1) % w.nu_every == 0:
-                c.nusselt(cur, self.w_, profile=self.prof[q], sync=False)
+                c.nusselt(self.ring[cur], self.w_, profile=self.prof[q], sync=False)
                 q += 1
-        return cur
+        return self.ring[cur]
 
 
-def time_runs(run, k, warmup, events=None):
+def time_runs(run, k, warmup, kernel_times=None):
+    """Wall time of k whole runs after warm-up; per-step kernel times (ms) from
+    event pairs recorded around each step launch are appended to kernel_times."""
     for _ in range(warmup):
         run.run()
     torch.cuda.synchronize()
+    pools = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(run.w.steps)] for _ in range(k)]
     t0 = time.perf_counter()
-    for _ in range(k):
-        run.run(events)
+    for r in range(k):
+        run.run(pools[r] if kernel_times is not None else None)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    el = time.perf_counter() - t0
+    if kernel_times is not None:
+        kernel_times.extend(a.elapsed_time(b) for pool in pools for a, b in pool)
+    return el
 
 
-def kernel_ms(events):
-    return float(np.mean([a.elapsed_time(b) for a, b in events]))
+def kernel_ms(times):
+    return float(np.mean(times))
 
 
 def copy_bandwidth():
@@ -173,7 +179,7 @@ def adjoint_times(steps_override=None):
     return float(np.median(tf)), float(np.median(tb)), N
 
 
-def cpu_baseline(w, budget_s=20.0):
+def cpu_baseline(w, budget_s=15.0):
     """The oracle's FP64 scalar step on the same workload, a bounded sample:
     as many whole-field steps as fit in the budget (at least one)."""
     import oracle as O
@@ -188,7 +194,7 @@ def cpu_baseline(w, budget_s=20.0):
         nxt = O.scalar_step(g, p, n, prev, cur, *uvw)
         prev, cur = cur, nxt
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 8:
+        if time.perf_counter() - t0 > budget_s or n >= 40:
             break
     el = time.perf_counter() - t0
     return dict(value=w.cells * n / el, unit="dense-cell updates/s", cores=1, kind="oracle",

@@ -185,6 +185,13 @@ class Context:
         check(lib().mr_scalar_step(self._ctx, c_int64(n), *args, _stream()), "mr_scalar_step", self._ctx)
         return out
 
+    def step_runner(self, ring, u, v, w):
+        """Prepared repeated stepping on fixed buffers: checks the buffers once
+        and caches their pointers and the current stream, so each step is one
+        library call.  ``ring`` is a list of scalar buffers; run.step(n, a, b, c)
+        computes ring[c] from ring[a] (level n-1) and ring[b] (level n)."""
+        return _StepRunner(self, ring, u, v, w)
+
     def adjoint_seed(self, n, lam, out):
         """mu^n = (I - tau_n kappa Lz)^-T lam."""
         check(lib().mr_adjoint_seed(self._ctx, c_int64(n), self._ptr(lam, self.shape_cell, "lam"),
@@ -230,6 +237,25 @@ class Context:
             return profile, None
         return profile, dict(nu_bot=out.nu_bot, nu_top=out.nu_top, nu_vol=out.nu_vol,
                              nu_paper=out.nu_paper, mean_theta=out.mean_theta)
+
+
+class _StepRunner:
+    def __init__(self, ctx, ring, u, v, w):
+        self._ctx = ctx
+        self._ring = list(ring)   # keep the tensors alive
+        self._p = [ctx._ptr(t, ctx.shape_cell, "ring[%d]" % q) for q, t in enumerate(ring)]
+        self._uvw = (ctx._ptr(u, ctx.shape_cell, "u"), ctx._ptr(v, ctx.shape_cell, "v"),
+                     ctx._ptr(w, ctx.shape_w, "w"))
+        self._keep = (u, v, w)
+        self._stream = _stream()
+        self._fn = lib().mr_scalar_step
+
+    def step(self, n, a, b, c):
+        if c == a or c == b:
+            raise ValueError("the output buffer must differ from the inputs")
+        st = self._fn(self._ctx._ctx, n, self._p[a], self._p[b], self._p[c], *self._uvw, self._stream)
+        if st:
+            check(st, "mr_scalar_step", self._ctx._ctx)
 
 
 def copy_probe(src, dst):

@@ -71,18 +71,31 @@ __device__ __forceinline__ void stb(T* base, unsigned boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
-template <typename T, int L, int MODE>
+// A wavefront covers 64/ROWS columns of ROWS consecutive y rows.  With
+// ROWS > 1 the y neighbours inside the patch are other lanes' centre values
+// (cross-lane shuffles), and one load per field fetches the two halo rows
+// (the row below the patch for its first row, the row above for its last).
+template <typename T, int L, int MODE, int ROWS, bool ROW_FAST>
 __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs<T> A) {
   __shared__ double sh[4][kMaxChunks][kWave];
+  constexpr int COLS = kWave / ROWS;
   const int lane = threadIdx.x;
   const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int ntx = (nx + kWave - 1) / kWave;
-  const int t = xcd_remap(blockIdx.x, ntx * ny);
-  const int xt = t % ntx, j = t / ntx;
-  const int i_raw = xt * kWave + lane;
-  const bool act = i_raw < nx;
-  const int i = act ? i_raw : nx - 1;
+  const int ntx = (nx + COLS - 1) / COLS, nty = (ny + ROWS - 1) / ROWS;
+  const int t = xcd_remap(blockIdx.x, ntx * nty);
+  // ROW_FAST: the workgroups resident on one XCD are consecutive row patches of
+  // one x strip; otherwise consecutive x tiles of one row patch
+  const int jt = ROW_FAST ? t % nty : t / ntx;
+  const int xt = ROW_FAST ? t / nty : t % ntx;
+  const int hrow = lane / COLS;
+  const int i_raw = xt * COLS + lane % COLS;
+  const int j_raw = jt * ROWS + hrow;
+  const bool act = i_raw < nx && j_raw < ny;
+  const int i = i_raw < nx ? i_raw : nx - 1;
+  // a row past the last one wraps around (periodic), so that the other half
+  // still sees the right neighbour row; its results are not stored
+  const int j = j_raw % ny;
   const int im = i == 0 ? nx - 1 : i - 1;
   const int ip = i == nx - 1 ? 0 : i + 1;
   const int jm = j == 0 ? ny - 1 : j - 1;
@@ -94,6 +107,9 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
   constexpr unsigned sz = sizeof(T);
   const unsigned oc = (j * nx + i) * sz, oxm = (j * nx + im) * sz, oxp = (j * nx + ip) * sz;
   const unsigned oym = (jm * nx + i) * sz, oyp = (jp * nx + i) * sz;
+  // ROWS > 1: the halo row of the patch (below for its first row, above otherwise)
+  const unsigned ohalo = hrow == 0 ? oym : oyp;
+  const int lane_dn = (lane - COLS) & (kWave - 1), lane_up = (lane + COLS) & (kWave - 1);
   const Geom<T>& g = A.g;
 
   const T ihx = g.ihx[i], ihxm = g.ihx[im], ihxp = g.ihx[ip];
@@ -130,11 +146,17 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
     const T* pk = p + kc * nxy;
     v.zp = ldb(f + min(k + 1, nz - 1) * nxy, oc);
     v.w1 = ldb(A.w + (kc + 1) * nxy, oc);
-    v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp); v.ym = ldb(fk, oym); v.yp = ldb(fk, oyp);
+    v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp);
     v.u0 = ldb(uk, oc); v.u1 = ldb(uk, oxp);
     v.v0 = ldb(vk, oc); v.v1 = ldb(vk, oyp);
     v.pc = ldb(pk, oc); v.pxm = ldb(pk, oxm); v.pxp = ldb(pk, oxp);
-    v.pym = ldb(pk, oym); v.pyp = ldb(pk, oyp);
+    if constexpr (ROWS == 1) {
+      v.ym = ldb(fk, oym); v.yp = ldb(fk, oyp);
+      v.pym = ldb(pk, oym); v.pyp = ldb(pk, oyp);
+    } else {
+      v.ym = ldb(fk, ohalo);   // halo row of f (resolved to ym/yp below)
+      v.pym = ldb(pk, ohalo);  // halo row of p
+    }
     if (MODE != FWD) v.q = ldb(A.a2 + kc * nxy, oc);
     return v;
   };
@@ -150,6 +172,15 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
     if (MODE == SEED) {
       r = cur.pc;
     } else {
+      if constexpr (ROWS > 1) {
+        const T fdn = __shfl(zc, lane_dn), fup = __shfl(zc, lane_up);
+        const T pdn = __shfl(cur.pc, lane_dn), pup = __shfl(cur.pc, lane_up);
+        const T fh = cur.ym, ph = cur.pym;
+        cur.ym = hrow == 0 ? fh : fdn;
+        cur.yp = hrow == ROWS - 1 ? fh : fup;
+        cur.pym = hrow == 0 ? ph : pdn;
+        cur.pyp = hrow == ROWS - 1 ? ph : pup;
+      }
       const T zp = cur.zp, w1 = cur.w1;
       const T ihz = g.ihz[kc];
       const T mlo = g.zlo[k], mhi = g.zhi[k];
@@ -229,15 +260,25 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
   }
 }
 
+// Measured on MI355X (rocprofv3 and event timing): FP64 runs best with two-row
+// patches walked rows-first, FP32 with single-row patches walked x-first.
+template <typename T>
+struct StepLayout {
+  static constexpr int rows = sizeof(T) == 8 ? 2 : 1;
+  static constexpr bool row_fast = sizeof(T) == 8;
+};
+
 template <typename T, int MODE>
 hipError_t launch_line(mr_ctx* c, const LineArgs<T>& a, hipStream_t s) {
-  const int ntx = (c->nx + kWave - 1) / kWave;
-  const dim3 grid((unsigned)(ntx * c->ny));
+  constexpr int rows = StepLayout<T>::rows, cols = kWave / rows;
+  constexpr bool rf = StepLayout<T>::row_fast;
+  const int ntx = (c->nx + cols - 1) / cols, nty = (c->ny + rows - 1) / rows;
+  const dim3 grid((unsigned)(ntx * nty));
   const dim3 block(kWave, c->nch);
   switch (c->L) {
-#define MR_CASE(LL)                                                       \
-  case LL:                                                                \
-    hipLaunchKernelGGL((line_kernel<T, LL, MODE>), grid, block, 0, s, a); \
+#define MR_CASE(LL)                                                             \
+  case LL:                                                                      \
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, rf>), grid, block, 0, s, a); \
     break;
     MR_CASE(8)
     MR_CASE(16)
