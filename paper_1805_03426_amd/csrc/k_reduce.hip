@@ -156,9 +156,28 @@ __global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const
   }
 }
 
+// One workgroup: Nu_k of every face from the partials (fixed order), then the
+// summary sums as a fixed tree (per-thread strided double-double sums, wave
+// shuffles, then the four waves in order).  Per-face values stay in LDS.
+constexpr int kNuMaxFaces = 1024;
+
+__device__ __forceinline__ DD block_sum(DD v, DD* scratch) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) scratch[wv] = v;
+  __syncthreads();
+  DD r = scratch[0];
+  for (int q = 1; q < (int)blockDim.x / kWave; ++q) r = dd_merge(r, scratch[q]);
+  return r;
+}
+
 __global__ void __launch_bounds__(256) nu_final(const double* part, int P, int nz,
                                                 const double* dcz, const double* hz, double atot,
-                                                double sq, double* mean_k, double* prof) {
+                                                double sq, double* prof) {
+  __shared__ double s_nu[kNuMaxFaces + 1];
+  __shared__ double s_mean[kNuMaxFaces];
+  __shared__ DD scratch[256 / kWave];
   for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
     DD conv{0.0, 0.0}, grad{0.0, 0.0}, mean{0.0, 0.0};
     for (int p = 0; p < P; ++p) {
@@ -168,22 +187,28 @@ __global__ void __launch_bounds__(256) nu_final(const double* part, int P, int n
       mean = dd_merge(mean, DD{o[4], o[5]});
     }
     const double cs = conv.s + conv.c, gs = grad.s + grad.c;
-    prof[k] = sq * (cs / atot) - (gs / dcz[k]) / atot;
-    if (k < nz) mean_k[k] = (mean.s + mean.c) * hz[k];
+    const double nu = sq * (cs / atot) - (gs / dcz[k]) / atot;
+    prof[k] = nu;
+    s_nu[k] = nu;
+    if (k < nz) s_mean[k] = (mean.s + mean.c) * hz[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    DD vol{0.0, 0.0}, pap{0.0, 0.0}, mt{0.0, 0.0}, hsum{0.0, 0.0};
-    for (int k = 0; k <= nz; ++k) {
-      vol = dd_add(vol, dcz[k] * prof[k]);
-      if (k > 0 && k < nz) pap = dd_add(pap, prof[k]);
-      if (k < nz) {
-        mt = dd_add(mt, mean_k[k]);
-        hsum = dd_add(hsum, hz[k]);
-      }
+  DD vol{0.0, 0.0}, pap{0.0, 0.0}, mt{0.0, 0.0}, hsum{0.0, 0.0};
+  for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
+    vol = dd_add(vol, dcz[k] * s_nu[k]);
+    if (k > 0 && k < nz) pap = dd_add(pap, s_nu[k]);
+    if (k < nz) {
+      mt = dd_add(mt, s_mean[k]);
+      hsum = dd_add(hsum, hz[k]);
     }
-    prof[nz + 1] = prof[0];
-    prof[nz + 2] = prof[nz];
+  }
+  vol = block_sum(vol, scratch);
+  pap = block_sum(pap, scratch);
+  mt = block_sum(mt, scratch);
+  hsum = block_sum(hsum, scratch);
+  if (threadIdx.x == 0) {
+    prof[nz + 1] = s_nu[0];
+    prof[nz + 2] = s_nu[nz];
     prof[nz + 3] = vol.s + vol.c;
     prof[nz + 4] = nz > 1 ? (pap.s + pap.c) / (nz - 1) : 0.0;
     prof[nz + 5] = (mt.s + mt.c) / (atot * (hsum.s + hsum.c));
@@ -234,9 +259,9 @@ hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void
 hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s) {
   const int P = nu_parts(c);
   const size_t part = (size_t)(c->nz + 1) * P * 6;
-  hipError_t e = ensure_red(c, sizeof(double) * (part + c->nz + 1));
+  if (c->nz > kNuMaxFaces) return hipErrorInvalidValue;
+  hipError_t e = ensure_red(c, sizeof(double) * part);
   if (e != hipSuccess) return e;
-  double* mean_k = c->red + part;
   const dim3 grid(P, c->nz + 1);
   const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
   if (c->precision == MR_FP64)
@@ -246,7 +271,7 @@ hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof
     hipLaunchKernelGGL(nu_partial<float>, grid, dim3(256), 0, s, (const float*)th, (const float*)w,
                        c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, c->red);
   hipLaunchKernelGGL(nu_final, dim3(1), dim3(256), 0, s, (const double*)c->red, P, c->nz, c->dcz,
-                     c->hz64, c->atot, sqrt(c->ra * c->pr), mean_k, prof);
+                     c->hz64, c->atot, sqrt(c->ra * c->pr), prof);
   return hipGetLastError();
 }
 

@@ -40,15 +40,6 @@ struct LineArgs {
   int nx, ny, nz, nch;
 };
 
-#ifndef MR_STEP_PREFETCH
-#define MR_STEP_PREFETCH 1
-#endif
-#ifndef MR_STEP_MIN_BLOCKS
-#define MR_STEP_MIN_BLOCKS 1
-#endif
-// Issue the loads of level k+1 before the arithmetic of level k.
-constexpr bool kPrefetch = MR_STEP_PREFETCH != 0;
-
 // Values one z level of the stencil reads.
 template <typename T>
 struct Lvl {
@@ -75,8 +66,8 @@ __device__ __forceinline__ void stb(T* base, unsigned boff, T v) {
 // ROWS > 1 the y neighbours inside the patch are other lanes' centre values
 // (cross-lane shuffles), and one load per field fetches the two halo rows
 // (the row below the patch for its first row, the row above for its last).
-template <typename T, int L, int MODE, int ROWS, bool ROW_FAST>
-__global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs<T> A) {
+template <typename T, int L, int MODE, int ROWS, bool ROW_FAST, int MINB, bool PREFETCH>
+__global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
   const int lane = threadIdx.x;
@@ -167,7 +158,7 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
     const int k = k0 + kk;
     const int kc = min(k, nz - 1);
     Lvl<T> nxt;
-    if (kPrefetch && kk + 1 < L) nxt = fetch(k + 1);   // next level's loads in flight
+    if (PREFETCH && kk + 1 < L) nxt = fetch(k + 1);   // next level's loads in flight
     T r;
     if (MODE == SEED) {
       r = cur.pc;
@@ -223,7 +214,7 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
       dprev = A.z.m[k] * ((double)r + A.z.tkb[k]) + A.z.a[k] * dprev;
       d[kk] = dprev;
     }
-    if (kk + 1 < L) cur = kPrefetch ? nxt : fetch(k + 1);
+    if (kk + 1 < L) cur = PREFETCH ? nxt : fetch(k + 1);
   }
   if (MODE == BWD0) return;
 
@@ -262,23 +253,33 @@ __global__ void __launch_bounds__(1024, MR_STEP_MIN_BLOCKS) line_kernel(LineArgs
 
 // Measured on MI355X (rocprofv3 and event timing): FP64 runs best with two-row
 // patches walked rows-first, FP32 with single-row patches walked x-first.
+#ifndef MR_F32_MINB
+#define MR_F32_MINB 1
+#endif
+#ifndef MR_F32_PREFETCH
+#define MR_F32_PREFETCH 1
+#endif
 template <typename T>
 struct StepLayout {
   static constexpr int rows = sizeof(T) == 8 ? 2 : 1;
   static constexpr bool row_fast = sizeof(T) == 8;
+  static constexpr int min_blocks = sizeof(T) == 8 ? 1 : MR_F32_MINB;   // minimum waves per SIMD
+  static constexpr bool prefetch = sizeof(T) == 8 ? true : MR_F32_PREFETCH != 0;  // loads of level k+1 before level k's arithmetic
 };
 
 template <typename T, int MODE>
 hipError_t launch_line(mr_ctx* c, const LineArgs<T>& a, hipStream_t s) {
   constexpr int rows = StepLayout<T>::rows, cols = kWave / rows;
   constexpr bool rf = StepLayout<T>::row_fast;
+  constexpr int mb = StepLayout<T>::min_blocks;
+  constexpr bool pf = StepLayout<T>::prefetch;
   const int ntx = (c->nx + cols - 1) / cols, nty = (c->ny + rows - 1) / rows;
   const dim3 grid((unsigned)(ntx * nty));
   const dim3 block(kWave, c->nch);
   switch (c->L) {
 #define MR_CASE(LL)                                                             \
   case LL:                                                                      \
-    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, rf>), grid, block, 0, s, a); \
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, rf, mb, pf>), grid, block, 0, s, a); \
     break;
     MR_CASE(8)
     MR_CASE(16)

@@ -1,0 +1,75 @@
+"""Oracle results for single dense columns of a large grid, computed on small
+windows (test infrastructure).
+
+On a grid that is uniform in x and y, the refinement of the coarse cells
+around coarse column (I, J) depends only on coarse columns I-3..I+3 and
+J-3..J+3, and one scalar step of dense column (i, j) only on the dense columns
+i-1..i+1, j-1..j+1 (all z).  A window of that size, treated as a small
+periodic domain with the same spacing, therefore gives the exact oracle
+values at its centre: the window's own wrap only touches columns that are
+discarded.  The window inputs are slices of the caller's arrays (generator
+output), never of GPU results.
+"""
+import numpy as np
+
+import oracle as O
+
+COARSE_RADIUS = 3
+
+
+def _take(a, axis, idx):
+    return np.take(a, idx, axis=axis, mode="wrap")
+
+
+def refine_window(U, V, W, m, zf, nx, ny, I, J):
+    """Oracle dense (u, v, w) of the dense columns inside coarse columns
+    I-1..I+1 and J-1..J+1; returns the dense window arrays and the global
+    dense index of their first x and y column."""
+    mx, my, mz = m
+    ncy, ncx = U.shape[1], U.shape[2]
+    r = COARSE_RADIUS
+    ci = np.arange(I - r, I + r + 1) % ncx
+    cj = np.arange(J - r, J + r + 1) % ncy
+    Uw = _take(_take(U, 2, ci), 1, cj)
+    Vw = _take(_take(V, 2, ci), 1, cj)
+    Ww = _take(_take(W, 2, ci), 1, cj)
+    n_win = 2 * r + 1
+    xf = np.arange(n_win * mx + 1) / nx
+    yf = np.arange(n_win * my + 1) / ny
+    g = O.Grid(xf, yf, zf, m)
+    u, v, w = O.refine_velocity(g, Uw, Vw, Ww)
+    return (u, v, w), ((I - r) * mx, (J - r) * my)
+
+
+def step_column(th_prev, th_cur, uvw_window, origin, zf, nx, ny, m, params, n, i, j):
+    """Oracle scalar step n for dense column (i, j): a 3x3-column window of the
+    scalar levels and of the window velocity around (i, j)."""
+    u, v, w = uvw_window
+    ox, oy = origin
+    li, lj = i - ox, j - oy            # position inside the velocity window
+    assert 1 <= li < u.shape[2] - 1 and 1 <= lj < u.shape[1] - 1
+    xs = np.arange(i - 1, i + 2) % nx
+    ys = np.arange(j - 1, j + 2) % ny
+    tp = _take(_take(th_prev, 2, xs), 1, ys)
+    tc = _take(_take(th_cur, 2, xs), 1, ys)
+    sl = (slice(None), slice(lj - 1, lj + 2), slice(li - 1, li + 2))
+    g = O.Grid(np.arange(4) / nx, np.arange(4) / ny, zf, (1, 1, 1))
+    out = O.scalar_step(g, params, n, tp, tc, u[sl], v[sl], w[sl])
+    return out[:, 1, 1]
+
+
+def dense_column(uvw_window, origin, i, j):
+    """(u, v, w) of dense column (i, j) from a refined window."""
+    u, v, w = uvw_window
+    li, lj = i - origin[0], j - origin[1]
+    return u[:, lj, li], v[:, lj, li], w[:, lj, li]
+
+
+def sample_columns(nx, ny, mx, my, count, seed):
+    """Seeded dense columns (i, j), spread over the grid, including the
+    periodic seam (first and last columns)."""
+    rng = np.random.default_rng(seed)
+    cols = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0)]
+    while len(cols) < count:
+        cols.append((int(rng.integers(nx)), int(rng.integers(ny))))
+    return cols

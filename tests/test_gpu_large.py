@@ -1,0 +1,210 @@
+"""Full-size GPU checks of the large workloads:
+
+* 192^3 -> 576^3 (M = 3), FP32 storage: refinement and steps on sampled
+  columns against the windowed oracle, and the FP32 tier against an FP64 GPU
+  run after 200 steps (scalar field and Nusselt numbers);
+* 512x512x256 -> 1024x1024x512, FP32: refinement and steps on sampled columns;
+* the adjoint workload (256^3, FP32, 20 steps, checkpoint every 5): gradients
+  of 0.5 ||theta_N - target||^2 against central differences of FP64 GPU
+  forward runs on 16 seeded directions, and an FP32 adjoint against the
+  oracle's discrete adjoint on a 32^3 -> 64^3 copy.
+
+The sampled oracle values come from small windows of the generator's inputs
+(tests/sampling.py); no expected value comes from a GPU result."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_03426_amd import inputs
+from paper_1805_03426_amd.configs import WORKLOADS
+from tests import sampling as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(d, w, precision, n_avg=None):
+    from paper_1805_03426_amd.context import Context
+    return Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"],
+                   n_avg=w.n_avg if n_avg is None else n_avg, precision=precision)
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _sampled_checks(w, d, ctx, dtype, tol_refine, tol_step, cols, th_cur, th_prev_cases):
+    """Refinement and steps of the GPU context on sampled columns vs the windowed oracle."""
+    nx, ny, nz = w.n
+    mx, my, mz = w.m
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    u, v, wv = ctx.interpolate_velocity(_dev(d["U"], dtype), _dev(d["V"], dtype), _dev(d["W"], dtype))
+    dth_cur = _dev(th_cur, dtype)
+    out = ctx.empty(ctx.shape_cell)
+    worst_r, worst_s = 0.0, 0.0
+    windows = {}
+    for (i, j) in cols:
+        win, origin = S.refine_window(d["U"], d["V"], d["W"], w.m, d["zf"], nx, ny, i // mx, j // my)
+        windows[(i, j)] = (win, origin)
+        want = S.dense_column(win, origin, i, j)
+        got = (u[:, j, i], v[:, j, i], wv[:, j, i])
+        for a, b in zip(got, want):
+            e = np.abs(a.double().cpu().numpy() - b).max() / max(np.abs(b).max(), 1e-300)
+            worst_r = max(worst_r, e)
+    assert worst_r <= tol_refine, worst_r
+    for n, th_prev in th_prev_cases:
+        ctx.scalar_step(n, _dev(th_prev, dtype), dth_cur, out, u, v, wv)
+        torch.cuda.synchronize()
+        got = np.stack([out[:, j, i].double().cpu().numpy() for (i, j) in cols])
+        want = np.stack([S.step_column(th_prev, th_cur, *windows[(i, j)], d["zf"], nx, ny, w.m, p, n, i, j)
+                         for (i, j) in cols])
+        e = _rel_l2(got, want)
+        worst_s = max(worst_s, e)
+        assert e <= tol_step, (n, e)
+    return worst_r, worst_s, (u, v, wv)
+
+
+def test_rb576_sampled_and_fp32_drift():
+    """576^3, M = 3, Pr = 100: sampled parity in FP64 and FP32, and the FP32
+    tier's error against the FP64 GPU run after 200 steps."""
+    print("case rb576 fp32/fp64 full size", flush=True)
+    w = WORKLOADS["rb576-m3-fp32"]
+    d = inputs.workload_inputs(w)
+    nx, ny, nz = w.n
+    cols = S.sample_columns(nx, ny, w.m[0], w.m[1], 6, seed=11)
+    th0 = d["theta0"]
+    cases = [(0, th0), (1, th0), (49, th0)]
+    with _ctx(d, w, "fp64") as c64, _ctx(d, w, "fp32") as c32:
+        r64, s64, uvw64 = _sampled_checks(w, d, c64, torch.float64, 1e-12, 1e-12, cols, th0, cases)
+        r32, s32, uvw32 = _sampled_checks(w, d, c32, torch.float32, 1e-5, 1e-5, cols, th0, cases)
+        print("rb576 sampled: refine fp64 %.2e fp32 %.2e; step fp64 %.2e fp32 %.2e" % (r64, r32, s64, s32),
+              flush=True)
+        # 200 steps, FP32 vs FP64, same seeded inputs (each context refines its own velocity)
+        ring64 = [_dev(th0, torch.float64)] + [c64.empty(c64.shape_cell) for _ in range(3)]
+        ring32 = [_dev(th0, torch.float32)] + [c32.empty(c32.shape_cell) for _ in range(3)]
+        run64 = c64.step_runner(ring64, *uvw64)
+        run32 = c32.step_runner(ring32, *uvw32)
+        prev = cur = 0
+        for n in range(w.steps):
+            out = 1 + n % 3
+            run64.step(n, prev, cur, out)
+            run32.step(n, prev, cur, out)
+            prev, cur = cur, out
+        a = ring32[cur].double()
+        b = ring64[cur]
+        ap, bp = ring32[prev].double(), ring64[prev]
+        zc = torch.from_numpy(0.5 * (d["zf"][1:] + d["zf"][:-1])).to("cuda")[:, None, None]
+        err_theta = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        err_fluct = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b - (1 - zc)))
+        err_incr = float(torch.linalg.vector_norm((a - ap) - (b - bp)) / torch.linalg.vector_norm(b - bp))
+        _, nu64 = c64.nusselt(b, uvw64[2])
+        _, nu32 = c32.nusselt(ring32[cur], uvw32[2])
+        nu_err = {k: abs(nu32[k] - nu64[k]) / abs(nu64[k]) for k in nu64}
+        print("rb576 fp32 vs fp64 after %d steps: theta %.3e, theta-(1-z) %.3e, last increment %.3e; Nu %s"
+              % (w.steps, err_theta, err_fluct, err_incr,
+                 ", ".join("%s %.2e" % kv for kv in nu_err.items())), flush=True)
+        assert err_theta < 1e-4 and err_fluct < 1e-2
+        assert max(nu_err.values()) < 1e-3
+
+
+def test_rb1024_fp32_sampled():
+    """1024x1024x512 FP32: refinement and steps on sampled columns."""
+    print("case rb1024x1024x512 fp32 full size", flush=True)
+    w = WORKLOADS["rb1024x1024x512-m2-fp32"]
+    d = inputs.workload_inputs(w)
+    nx, ny, nz = w.n
+    cols = S.sample_columns(nx, ny, w.m[0], w.m[1], 5, seed=12)
+    th0 = d["theta0"]
+    with _ctx(d, w, "fp32") as c32:
+        r, s, _ = _sampled_checks(w, d, c32, torch.float32, 1e-5, 1e-5, cols, th0,
+                                  [(0, th0), (1, th0), (49, th0)])
+    print("rb1024x1024x512 sampled: refine %.2e step %.2e" % (r, s), flush=True)
+
+
+def _fp64_loss(c64, d, th0, U, V, W, N, target):
+    """0.5 ||theta_N - target||^2 of an FP64 GPU forward run."""
+    u, v, w = c64.interpolate_velocity(U, V, W)
+    ring = [th0] + [c64.empty(c64.shape_cell) for _ in range(3)]
+    run = c64.step_runner(ring, u, v, w)
+    prev = cur = 0
+    for n in range(N):
+        out = 1 + n % 3
+        run.step(n, prev, cur, out)
+        prev, cur = cur, out
+    r = ring[cur] - target
+    return 0.5 * float(torch.sum(r * r))
+
+
+def test_adjoint_rb256_fp32_against_finite_differences():
+    """FP32 gradients (checkpointed rollout) vs central differences (eps =
+    1e-3) of FP64 GPU forward runs on 16 seeded directions."""
+    print("case adjoint rb256 fp32 vs fd", flush=True)
+    from paper_1805_03426_amd.autograd import rollout
+    w = WORKLOADS["rb256-m2-adjoint-fp32"]
+    d = inputs.workload_inputs(w)
+    nx, ny, nz = w.n
+    target = inputs.theta_initial(d["zf"], nx, ny, seed=inputs.SEED_TARGET)
+    N = w.steps
+    with _ctx(d, w, "fp32") as c32:
+        th = _dev(d["theta0"], torch.float32).requires_grad_(True)
+        U, V, W = (_dev(d[k], torch.float32).requires_grad_(True) for k in ("U", "V", "W"))
+        out = rollout(c32, th, U, V, W, N, w.ckpt_every)
+        tg = _dev(target, torch.float32)
+        torch.autograd.backward(out, out.detach() - tg)
+        gth, gU, gV, gW = (t.grad.double() for t in (th, U, V, W))
+    rng = np.random.default_rng(inputs.SEED_DIRECTIONS)
+    xf, yf, zf = d["xf"], d["yf"], d["zf"]
+    mx, my, mz = w.m
+    eps = 1e-3
+    worst = 0.0
+    with _ctx(d, w, "fp64") as c64:
+        th64 = _dev(d["theta0"], torch.float64)
+        U64, V64, W64 = (_dev(d[k], torch.float64) for k in ("U", "V", "W"))
+        tg64 = _dev(target, torch.float64)
+        for q in range(16):
+            dth = rng.standard_normal(d["theta0"].shape)
+            dth /= np.sqrt(np.mean(dth * dth))
+            dU, dV, dW = inputs.divergence_free_velocity(xf[::mx], yf[::my], zf[::mz], kmax=4, urms=1.0,
+                                                          seed=40 + q)
+            dirs = [_dev(a, torch.float64) for a in (dth, dU, dV, dW)]
+            lp = _fp64_loss(c64, d, th64 + eps * dirs[0], U64 + eps * dirs[1], V64 + eps * dirs[2],
+                            W64 + eps * dirs[3], N, tg64)
+            lm = _fp64_loss(c64, d, th64 - eps * dirs[0], U64 - eps * dirs[1], V64 - eps * dirs[2],
+                            W64 - eps * dirs[3], N, tg64)
+            fd = (lp - lm) / (2 * eps)
+            ad = float(sum(torch.sum(g * t) for g, t in zip((gth, gU, gV, gW), dirs)))
+            rel = abs(ad - fd) / abs(fd)
+            worst = max(worst, rel)
+            assert rel < 2e-3, (q, ad, fd, rel)
+    print("adjoint rb256 fp32 vs fp64 central differences: worst relative error %.2e over 16 directions"
+          % worst, flush=True)
+
+
+def test_adjoint_fp32_against_oracle_rb64():
+    """FP32 checkpointed adjoint on the 32^3 -> 64^3 copy against the oracle's
+    FP64 discrete adjoint (20 steps)."""
+    print("case adjoint rb64 fp32 vs oracle", flush=True)
+    from paper_1805_03426_amd.autograd import rollout
+    w = WORKLOADS["rb64-m2-fp64"]
+    d = inputs.workload_inputs(w)
+    nx, ny, nz = w.n
+    N = 20
+    target = inputs.theta_initial(d["zf"], nx, ny, seed=inputs.SEED_TARGET)
+    g = O.Grid(d["xf"], d["yf"], d["zf"], w.m)
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(g, p, d["theta0"], d["U"], d["V"], d["W"], N, target)
+    with _ctx(d, w, "fp32") as c32:
+        th = _dev(d["theta0"], torch.float32).requires_grad_(True)
+        U, V, W = (_dev(d[k], torch.float32).requires_grad_(True) for k in ("U", "V", "W"))
+        out = rollout(c32, th, U, V, W, N, 5)
+        torch.autograd.backward(out, out.detach() - _dev(target, torch.float32))
+        got = [t.grad.double().cpu().numpy() for t in (th, U, V, W)]
+    for a, b in zip(got, (w0, wU, wV, wW)):
+        e = _rel_l2(a, b)
+        assert e < 1e-4, e
