@@ -38,6 +38,7 @@ struct LineArgs {
   T ap1, tk1;          // BWD: a_p(n+1), tau_{n+1} kappa (0 when there is no step n+1)
   T s2;                // BWD: 1 with lam_add, 0 without
   int nx, ny, nz, nch;
+  int band;            // x tiles per band of the tile walk (see line_kernel)
 };
 
 // Values one z level of the stencil reads.
@@ -62,11 +63,48 @@ __device__ __forceinline__ void stb(T* base, unsigned boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives
+// the value of lane l-1 (shr) or l+1 (shl); the lane with no source keeps its
+// own value, which every caller replaces.
+__device__ __forceinline__ int dpp_shr_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_shr(float v) { return __int_as_float(dpp_shr_i(__float_as_int(v))); }
+__device__ __forceinline__ float lane_shl(float v) { return __int_as_float(dpp_shl_i(__float_as_int(v))); }
+__device__ __forceinline__ double lane_shr(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = dpp_shr_i((int)x), hi = dpp_shr_i((int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_shl(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = dpp_shl_i((int)x), hi = dpp_shl_i((int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+#ifndef MR_XDPP
+#define MR_XDPP 1
+#endif
+
 // A wavefront covers 64/ROWS columns of ROWS consecutive y rows.  With
 // ROWS > 1 the y neighbours inside the patch are other lanes' centre values
 // (cross-lane shuffles), and one load per field fetches the two halo rows
 // (the row below the patch for its first row, the row above for its last).
-template <typename T, int L, int MODE, int ROWS, bool ROW_FAST, int MINB, bool PREFETCH>
+// The x neighbours are the centre values of the lanes beside it (lane
+// shifts); only the first and last column of each row load their outer
+// neighbour, in the same load instruction in which the other lanes re-read
+// their own (already cached) centre.  Lanes past the end of a ragged row take
+// the periodic continuation of the row (column i mod nx), so the lane after
+// the last column holds column 0, the periodic right neighbour of the last
+// column; such lanes never store.
+//
+// Tile walk: the x tiles are grouped into bands of A.band tiles; a band is
+// walked row patch by row patch, x fastest inside the band.  Workgroups that
+// run together on one XCD (consecutive after the XCD remap) then cover a few
+// tiles in x and many rows in y, so the y neighbour rows of one workgroup are
+// the centre rows of another that reads them at nearly the same time (L2
+// hits), while the lines holding the x halo of a tile are shared with the
+// tiles beside it in the band.
+template <typename T, int L, int MODE, int ROWS, int MINB, int PFD>
 __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
@@ -75,15 +113,17 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int ntx = (nx + COLS - 1) / COLS, nty = (ny + ROWS - 1) / ROWS;
   const int t = xcd_remap(blockIdx.x, ntx * nty);
-  // ROW_FAST: the workgroups resident on one XCD are consecutive row patches of
-  // one x strip; otherwise consecutive x tiles of one row patch
-  const int jt = ROW_FAST ? t % nty : t / ntx;
-  const int xt = ROW_FAST ? t / nty : t % ntx;
+  const int per_band = A.band * nty;
+  const int bnd = t / per_band;
+  const int rt = t - bnd * per_band;
+  const int wb = min(A.band, ntx - bnd * A.band);   // the last band may be narrower
+  const int jt = rt / wb;
+  const int xt = bnd * A.band + (rt - jt * wb);
   const int hrow = lane / COLS;
   const int i_raw = xt * COLS + lane % COLS;
   const int j_raw = jt * ROWS + hrow;
   const bool act = i_raw < nx && j_raw < ny;
-  const int i = i_raw < nx ? i_raw : nx - 1;
+  const int i = i_raw % nx;
   // a row past the last one wraps around (periodic), so that the other half
   // still sees the right neighbour row; its results are not stored
   const int j = j_raw % ny;
@@ -100,6 +140,11 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   const unsigned oym = (jm * nx + i) * sz, oyp = (jp * nx + i) * sz;
   // ROWS > 1: the halo row of the patch (below for its first row, above otherwise)
   const unsigned ohalo = hrow == 0 ? oym : oyp;
+  // first / last column of a row: its outer x neighbour; other lanes: their centre
+  const int col = lane % COLS;
+  const bool xfirst = col == 0, xlast = col == COLS - 1;
+  const unsigned oedge = xfirst ? oxm : (xlast ? oxp : oc);
+  const unsigned oedge_r = xlast ? oxp : oc;
   const int lane_dn = (lane - COLS) & (kWave - 1), lane_up = (lane + COLS) & (kWave - 1);
   const Geom<T>& g = A.g;
 
@@ -137,10 +182,18 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
     const T* pk = p + kc * nxy;
     v.zp = ldb(f + min(k + 1, nz - 1) * nxy, oc);
     v.w1 = ldb(A.w + (kc + 1) * nxy, oc);
-    v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp);
-    v.u0 = ldb(uk, oc); v.u1 = ldb(uk, oxp);
+    if constexpr (MR_XDPP) {
+      v.xm = ldb(fk, oedge);     // edge values, resolved after the lane shifts
+      v.u1 = ldb(uk, oedge_r);
+      v.pxm = ldb(pk, oedge);
+    } else {
+      v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp);
+      v.u1 = ldb(uk, oxp);
+      v.pxm = ldb(pk, oxm); v.pxp = ldb(pk, oxp);
+    }
+    v.u0 = ldb(uk, oc);
     v.v0 = ldb(vk, oc); v.v1 = ldb(vk, oyp);
-    v.pc = ldb(pk, oc); v.pxm = ldb(pk, oxm); v.pxp = ldb(pk, oxp);
+    v.pc = ldb(pk, oc);
     if constexpr (ROWS == 1) {
       v.ym = ldb(fk, oym); v.yp = ldb(fk, oyp);
       v.pym = ldb(pk, oym); v.pyp = ldb(pk, oyp);
@@ -152,17 +205,31 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
     return v;
   };
 
+  // PFD levels ahead of the one being computed have their loads in flight
   Lvl<T> cur = fetch(k0);
+  Lvl<T> n1, n2;
+  if (PFD >= 2 && L > 1) n1 = fetch(k0 + 1);
 #pragma unroll
   for (int kk = 0; kk < L; ++kk) {
     const int k = k0 + kk;
     const int kc = min(k, nz - 1);
-    Lvl<T> nxt;
-    if (PREFETCH && kk + 1 < L) nxt = fetch(k + 1);   // next level's loads in flight
+    if (PFD == 1 && kk + 1 < L) n1 = fetch(k + 1);
+    if (PFD == 2 && kk + 2 < L) n2 = fetch(k + 2);
     T r;
     if (MODE == SEED) {
       r = cur.pc;
     } else {
+      if constexpr (MR_XDPP) {
+        const T fe = cur.xm, pe = cur.pxm, ue = cur.u1;
+        const T fl = lane_shr(zc), fr = lane_shl(zc);
+        const T pl = lane_shr(cur.pc), pr = lane_shl(cur.pc);
+        const T ur = lane_shl(cur.u0);
+        cur.xm = xfirst ? fe : fl;
+        cur.xp = xlast ? fe : fr;
+        cur.pxm = xfirst ? pe : pl;
+        cur.pxp = xlast ? pe : pr;
+        cur.u1 = xlast ? ue : ur;
+      }
       if constexpr (ROWS > 1) {
         const T fdn = __shfl(zc, lane_dn), fup = __shfl(zc, lane_up);
         const T pdn = __shfl(cur.pc, lane_dn), pup = __shfl(cur.pc, lane_up);
@@ -214,7 +281,14 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
       dprev = A.z.m[k] * ((double)r + A.z.tkb[k]) + A.z.a[k] * dprev;
       d[kk] = dprev;
     }
-    if (kk + 1 < L) cur = PREFETCH ? nxt : fetch(k + 1);
+    if (kk + 1 < L) {
+      if (PFD == 0) {
+        cur = fetch(k + 1);
+      } else {
+        cur = n1;
+        if (PFD == 2) n1 = n2;
+      }
+    }
   }
   if (MODE == BWD0) return;
 
@@ -251,35 +325,49 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   }
 }
 
-// Measured on MI355X (rocprofv3 and event timing): FP64 runs best with two-row
-// patches walked rows-first, FP32 with single-row patches walked x-first.
+// Patch shape and tile walk per precision (timed on MI355X).
+#ifndef MR_ROWS64
+#define MR_ROWS64 2
+#endif
+#ifndef MR_ROWS32
+#define MR_ROWS32 1
+#endif
+#ifndef MR_BAND64
+#define MR_BAND64 1
+#endif
+#ifndef MR_BAND32
+#define MR_BAND32 4
+#endif
 #ifndef MR_F32_MINB
 #define MR_F32_MINB 1
 #endif
-#ifndef MR_F32_PREFETCH
-#define MR_F32_PREFETCH 1
+#ifndef MR_PFD64
+#define MR_PFD64 0
+#endif
+#ifndef MR_PFD32
+#define MR_PFD32 1
 #endif
 template <typename T>
 struct StepLayout {
-  static constexpr int rows = sizeof(T) == 8 ? 2 : 1;
-  static constexpr bool row_fast = sizeof(T) == 8;
+  static constexpr int rows = sizeof(T) == 8 ? MR_ROWS64 : MR_ROWS32;
+  static constexpr int band = sizeof(T) == 8 ? MR_BAND64 : MR_BAND32;   // 0: whole rows
   static constexpr int min_blocks = sizeof(T) == 8 ? 1 : MR_F32_MINB;   // minimum waves per SIMD
-  static constexpr bool prefetch = sizeof(T) == 8 ? true : MR_F32_PREFETCH != 0;  // loads of level k+1 before level k's arithmetic
+  static constexpr int prefetch = sizeof(T) == 8 ? MR_PFD64 : MR_PFD32;  // levels whose loads run ahead of the arithmetic
 };
 
 template <typename T, int MODE>
-hipError_t launch_line(mr_ctx* c, const LineArgs<T>& a, hipStream_t s) {
+hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   constexpr int rows = StepLayout<T>::rows, cols = kWave / rows;
-  constexpr bool rf = StepLayout<T>::row_fast;
   constexpr int mb = StepLayout<T>::min_blocks;
-  constexpr bool pf = StepLayout<T>::prefetch;
+  constexpr int pf = StepLayout<T>::prefetch;
   const int ntx = (c->nx + cols - 1) / cols, nty = (c->ny + rows - 1) / rows;
+  a.band = StepLayout<T>::band > 0 && StepLayout<T>::band < ntx ? StepLayout<T>::band : ntx;
   const dim3 grid((unsigned)(ntx * nty));
   const dim3 block(kWave, c->nch);
   switch (c->L) {
 #define MR_CASE(LL)                                                             \
   case LL:                                                                      \
-    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, rf, mb, pf>), grid, block, 0, s, a); \
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf>), grid, block, 0, s, a); \
     break;
     MR_CASE(8)
     MR_CASE(16)
