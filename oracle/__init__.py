@@ -19,7 +19,12 @@ finite-volume code for active or passive scalar turbulence"):
                   (Eqs. 2, 5), the Euler-leapfrog step with the averaging step
                   every N_p steps (Eqs. 6, 7) with z-diffusion implicit, the
                   Nusselt diagnostics (Eq. 22), and the discrete adjoint of a
-                  step and of a whole rollout.
+                  step and of a whole rollout;
+* ``intergrid`` -- the volume-weighted dense-to-coarse integration of the
+                  scalar (Eq. 20), the linear-in-time coarse velocity of the
+                  temporal strategy (Eq. 21), one coarse step of the
+                  multiple-resolution loop (Fig. 6), and the dissipation
+                  Nusselt number Nu_T (Eq. 23).
 
 Pins (tests marked ``not gpu``) tie every function to closed forms, invariants
 and brute force; see each function's docstring for the passage it follows.
@@ -30,8 +35,10 @@ from .refine import (r_matrix, stencil_start, refine_velocity, refine_velocity_t
                      divergence, split)
 from .scalar import (ScalarParams, step_kind, z_matrix, thomas, advection, lap_h, scalar_step,
                      nusselt, step_vjp, rollout, rollout_loss_grad)
+from .intergrid import integrate_scalar, blend_velocity, coarse_step, thermal_dissipation
 
 __all__ = ["Axis", "Grid", "r_matrix", "stencil_start", "refine_velocity",
            "refine_velocity_transpose", "divergence", "split", "ScalarParams", "step_kind",
            "z_matrix", "thomas", "advection", "lap_h", "scalar_step", "nusselt", "step_vjp",
-           "rollout", "rollout_loss_grad"]
+           "rollout", "rollout_loss_grad", "integrate_scalar", "blend_velocity", "coarse_step",
+           "thermal_dissipation"]
