@@ -12,7 +12,11 @@
  *     (Eqs. 2 and 5) in the Euler-leapfrog integrator with the averaging step
  *     every N_p steps (Eqs. 6 and 7), x/y diffusion explicit on level n-1 and
  *     z diffusion implicit on level n+1 (one tridiagonal solve per (x, y) line);
- *   - reports the heat-flux Nusselt profile (Eq. 22) and the mean scalar;
+ *   - reports the heat-flux Nusselt profile (Eq. 22), the mean scalar and the
+ *     dissipation Nusselt number Nu_T (Eq. 23);
+ *   - runs the inter-grid steps of the multiple-resolution loop: the coarse
+ *     velocity interpolated in time (Eq. 21), the dense-to-coarse integration
+ *     of the scalar (Eq. 20), and whole coarse steps of M_t scalar steps;
  *   - provides the discrete adjoint of the step and of the refinement.
  *
  * Conventions
@@ -185,6 +189,55 @@ int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps,
  * value is NaN or Inf. */
 int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
                mr_nu* host_out, void* stream);
+
+/* Dissipation Nusselt number (Sec. 4.1, Eq. 23): Nu_T = eps_T (Ra Pr)^(1/2) with
+ * eps_T = kappa <|grad theta|^2>_V, the volume mean of the squared gradient
+ * summed face by face: each face adds its squared difference quotient times
+ * its dual volume (face area times the centre distance across it); a
+ * Dirichlet plate uses the wall value at half a cell, an adiabatic plate adds
+ * nothing.  dev_out (device, 4 doubles) receives {Nu_T, <theta_x^2>,
+ * <theta_y^2>, <theta_z^2>} (volume means of the three squared components).
+ * Compensated sums in a fixed order.  host_out (4 doubles or NULL) as for
+ * mr_nusselt: the call then waits and reports MR_ENONFINITE for NaN/Inf. */
+int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, double* host_out,
+                           void* stream);
+
+/* ------------------------------------------------- inter-grid steps (Secs. 3.3-3.4) */
+
+/* Coarse velocity at fraction s = i/mt of a coarse step, refined to the dense
+ * faces (temporal strategy, Sec. 3.4, Eq. 21, read as the linear interpolation
+ * between the two coarse levels): refines (1 - s)(U0, V0, W0) + s (U1, V1, W1)
+ * as mr_interpolate_velocity does, the interpolation fused into its first
+ * stage.  0 <= i <= mt, mt >= 1; i = mt gives exactly the refinement of
+ * (U1, V1, W1), i = 0 that of (U0, V0, W0).  Two divergence-free levels give a
+ * divergence-free result (to rounding).  Outputs must not alias inputs. */
+int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, const void* W0,
+                                 const void* U1, const void* V1, const void* W1, int64_t i,
+                                 int64_t mt, void* u, void* v, void* w, void* stream);
+
+/* Upscale integration of the scalar (Sec. 3.3, Eq. 20, read as the
+ * volume-weighted mean of the cell averages): theta_c[K][J][I] = (sum over the
+ * mx*my*mz sub-cells of theta * hx*hy*hz) / (coarse cell volume).
+ * theta [nz][ny][nx] -> theta_c [ncz][ncy][ncx], the context's element type;
+ * sums in double.  theta_c must not alias theta. */
+int mr_integrate_scalar(mr_ctx* ctx, const void* theta, void* theta_c, void* stream);
+
+/* One coarse step of the multiple-resolution loop for the scalar (Fig. 6):
+ * for i = 1..mt, refine the coarse velocity at fraction i/mt into (u, v, w)
+ * (as mr_interpolate_velocity_time) and take scalar step n0 + i - 1 (as
+ * mr_scalar_step; the context's dt is the scalar step, i.e. the coarse step
+ * divided by mt); then, if theta_c is not NULL, integrate the newest scalar
+ * into theta_c (as mr_integrate_scalar).
+ * ring: host array of three distinct device scalar buffers.  On entry
+ * ring[*cur] holds theta^{n0} and, for n0 > 0, ring[*prev] holds theta^{n0-1}
+ * (at n0 = 0, *prev is ignored and may equal *cur).  On return *prev and *cur
+ * index theta^{n0+mt-1} and theta^{n0+mt}.  u, v, w are dense velocity
+ * buffers the call overwrites.  n0 >= 0, mt >= 1.  All work is enqueued on
+ * the stream; nothing is allocated beyond the context's refinement buffers. */
+int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const void* V0,
+                   const void* W0, const void* U1, const void* V1, const void* W1, void* u, void* v,
+                   void* w, void* const* ring, int32_t* prev, int32_t* cur, void* theta_c,
+                   void* stream);
 
 /* ------------------------------------------------------------ utilities */
 

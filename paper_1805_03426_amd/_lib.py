@@ -20,6 +20,8 @@ EXPORTS = [
     "mr_divergence", "mr_scalar_step", "mr_adjoint_seed", "mr_scalar_step_backward",
     "mr_velocity_grad", "mr_nusselt", "mr_copy_probe", "mr_host_refinement_table",
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
+    "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
+    "mr_coarse_step",
 ]
 
 
@@ -80,6 +82,11 @@ def lib():
                                      POINTER(c_void_p), P, P, P, P]),
         "mr_nusselt": (c_int, [P, P, P, P, POINTER(mr_nu), P]),
         "mr_copy_probe": (c_int, [P, P, c_int64, P]),
+        "mr_thermal_dissipation": (c_int, [P, P, P, POINTER(c_double), P]),
+        "mr_interpolate_velocity_time": (c_int, [P, P, P, P, P, P, P, c_int64, c_int64, P, P, P, P]),
+        "mr_integrate_scalar": (c_int, [P, P, P, P]),
+        "mr_coarse_step": (c_int, [P, c_int64, c_int32, P, P, P, P, P, P, P, P, P, POINTER(c_void_p),
+                                   POINTER(c_int32), POINTER(c_int32), P, P]),
         "mr_host_refinement_table": (c_int, [POINTER(mr_desc), c_int32, POINTER(c_double),
                                              POINTER(c_int32)]),
         "mr_host_z_system": (c_int, [POINTER(mr_desc), c_int64, POINTER(c_double),

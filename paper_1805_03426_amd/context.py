@@ -166,6 +166,50 @@ class Context:
               "mr_interpolate_velocity_backward", self._ctx)
         return gU, gV, gW
 
+    def interpolate_velocity_time(self, U0, V0, W0, U1, V1, W1, i, mt, out=None):
+        """Dense velocity at fraction i/mt of a coarse step: the refinement of
+        (1 - i/mt) (U0, V0, W0) + (i/mt) (U1, V1, W1)."""
+        if out is None:
+            out = (self.empty(self.shape_cell), self.empty(self.shape_cell), self.empty(self.shape_w))
+        u, v, w = out
+        cs, cw = self.shape_coarse, self.shape_coarse_w
+        args = [self._ptr(U0, cs, "U0"), self._ptr(V0, cs, "V0"), self._ptr(W0, cw, "W0"),
+                self._ptr(U1, cs, "U1"), self._ptr(V1, cs, "V1"), self._ptr(W1, cw, "W1"),
+                c_int64(i), c_int64(mt), self._ptr(u, self.shape_cell, "u"),
+                self._ptr(v, self.shape_cell, "v"), self._ptr(w, self.shape_w, "w")]
+        check(lib().mr_interpolate_velocity_time(self._ctx, *args, _stream()),
+              "mr_interpolate_velocity_time", self._ctx)
+        return u, v, w
+
+    def integrate_scalar(self, theta, out=None):
+        """Coarse scalar: volume-weighted mean of theta over each coarse cell."""
+        if out is None:
+            out = self.empty(self.shape_coarse)
+        check(lib().mr_integrate_scalar(self._ctx, self._ptr(theta, self.shape_cell, "theta"),
+                                        self._ptr(out, self.shape_coarse, "out"), _stream()),
+              "mr_integrate_scalar", self._ctx)
+        return out
+
+    def coarse_step(self, n0, mt, U0, V0, W0, U1, V1, W1, uvw, ring, prev, cur, theta_c=None):
+        """One coarse step (mt scalar steps on the time-interpolated, refined
+        velocity, then the integration of the newest scalar into theta_c).
+        ``ring`` holds three scalar buffers; ring[cur] is theta^{n0}, ring[prev]
+        theta^{n0-1}.  Returns the new (prev, cur) indices."""
+        if len(ring) != 3:
+            raise ValueError("ring must hold three scalar buffers")
+        cs, cw = self.shape_coarse, self.shape_coarse_w
+        u, v, w = uvw
+        rp = (c_void_p * 3)(*[self._ptr(t, self.shape_cell, "ring[%d]" % q).value for q, t in enumerate(ring)])
+        p, c = c_int32(prev), c_int32(cur)
+        args = [self._ptr(U0, cs, "U0"), self._ptr(V0, cs, "V0"), self._ptr(W0, cw, "W0"),
+                self._ptr(U1, cs, "U1"), self._ptr(V1, cs, "V1"), self._ptr(W1, cw, "W1"),
+                self._ptr(u, self.shape_cell, "u"), self._ptr(v, self.shape_cell, "v"),
+                self._ptr(w, self.shape_w, "w"), rp, byref(p), byref(c),
+                self._ptr(theta_c, cs, "theta_c")]
+        check(lib().mr_coarse_step(self._ctx, c_int64(n0), c_int32(mt), *args, _stream()),
+              "mr_coarse_step", self._ctx)
+        return p.value, c.value
+
     def divergence(self, u, v, w, out=None):
         """Device tensor [max |net flux|, max |net flux| / sum |face flux|] (float64)."""
         if out is None:
@@ -237,6 +281,20 @@ class Context:
             return profile, None
         return profile, dict(nu_bot=out.nu_bot, nu_top=out.nu_top, nu_vol=out.nu_vol,
                              nu_paper=out.nu_paper, mean_theta=out.mean_theta)
+
+
+    def thermal_dissipation(self, theta, out=None, sync=True):
+        """Device tensor {Nu_T, <theta_x^2>, <theta_y^2>, <theta_z^2>} (float64);
+        with sync=True also returns them as a dict."""
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=self.device)
+        host = (c_double * 4)() if sync else None
+        st = lib().mr_thermal_dissipation(self._ctx, self._ptr(theta, self.shape_cell, "theta"),
+                                          self._ptr(out, (4,), "out", torch.float64), host, _stream())
+        check(st, "mr_thermal_dissipation", self._ctx)
+        if not sync:
+            return out, None
+        return out, dict(nu_t=host[0], gx2=host[1], gy2=host[2], gz2=host[3])
 
 
 class _StepRunner:

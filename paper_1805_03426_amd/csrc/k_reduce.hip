@@ -13,34 +13,8 @@
 namespace mr {
 namespace {
 
-// ------------------------------------------------------- double-double sums
-struct DD {
-  double s, c;
-};
-
-__device__ __forceinline__ DD dd_add(DD a, double b) {
-  const double t = a.s + b;
-  const double bp = t - a.s;
-  const double e = (a.s - (t - bp)) + (b - bp);
-  return {t, a.c + e};
-}
-
-__device__ __forceinline__ DD dd_merge(DD a, DD b) {
-  DD r = dd_add(a, b.s);
-  r.c += b.c;
-  return r;
-}
-
 __device__ __forceinline__ double shfl_down_d(double v, int off) {
   return __shfl_down(v, off, kWave);
-}
-
-__device__ __forceinline__ DD wave_sum(DD v) {
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    DD o{shfl_down_d(v.s, off), shfl_down_d(v.c, off)};
-    v = dd_merge(v, o);
-  }
-  return v;
 }
 
 // ------------------------------------------------------------- divergence
@@ -222,6 +196,14 @@ __global__ void __launch_bounds__(256) copy_kernel(const int4* __restrict__ src,
     dst[t] = src[t];
 }
 
+int nu_parts(const mr_ctx* c) {
+  const int64_t nxy = (int64_t)c->nx * c->ny;
+  int64_t P = (nxy + 256 * 16 - 1) / (256 * 16);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(P, 64));
+}
+
+}  // namespace
+
 hipError_t ensure_red(mr_ctx* c, size_t bytes) {
   if (c->red_bytes >= bytes) return hipSuccess;
   if (c->red) (void)hipFree(c->red);
@@ -231,14 +213,6 @@ hipError_t ensure_red(mr_ctx* c, size_t bytes) {
   if (e == hipSuccess) c->red_bytes = bytes;
   return e;
 }
-
-int nu_parts(const mr_ctx* c) {
-  const int64_t nxy = (int64_t)c->nx * c->ny;
-  int64_t P = (nxy + 256 * 16 - 1) / (256 * 16);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(P, 64));
-}
-
-}  // namespace
 
 hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void* w, double* out,
                              hipStream_t s) {

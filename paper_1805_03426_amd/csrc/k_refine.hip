@@ -23,6 +23,10 @@ struct RefArgs {
   const T* in0;
   const T* in1;
   const T* in2;
+  const T* in3;   // stage z: second coarse velocity level (U^n, V^n, W^n) or null
+  const T* in4;
+  const T* in5;
+  T s;            // stage z: fraction of the coarse step (weight of the second level)
   T* out0;
   T* out1;
   T* out2;
@@ -40,6 +44,14 @@ __device__ __forceinline__ T rdot(const T* R, const T q[3]) {
 }
 
 // ---------------------------------------------------------------- forward
+// Coarse velocity value at index q; with a second level present, the linear
+// interpolation in time (1 - s) level0 + s level1 of the temporal strategy
+// (Eq. 21, read as interpolation between the two coarse levels).
+template <typename T>
+__device__ __forceinline__ T coarse_at(const T* a, const T* b, T s, int q) {
+  return b ? (T(1) - s) * a[q] + s * b[q] : a[q];
+}
+
 // stage z: thread per coarse cell (I, J, K)
 template <typename T>
 __global__ void __launch_bounds__(256) stage_z(RefArgs<T> A) {
@@ -52,16 +64,17 @@ __global__ void __launch_bounds__(256) stage_z(RefArgs<T> A) {
   const T* U = A.in0;
   const T* V = A.in1;
   const T* W = A.in2;
+  const T s = A.s;
   T u0[3], u1[3], v0[3], v1[3];
   for (int r = 0; r < 3; ++r) {
     const int kc = A.g.sz[K * 3 + r];
-    u0[r] = U[kc * ncxy + J * ncx + I];
-    u1[r] = U[kc * ncxy + J * ncx + Ip];
-    v0[r] = V[kc * ncxy + J * ncx + I];
-    v1[r] = V[kc * ncxy + Jp * ncx + I];
+    u0[r] = coarse_at(U, A.in3, s, kc * ncxy + J * ncx + I);
+    u1[r] = coarse_at(U, A.in3, s, kc * ncxy + J * ncx + Ip);
+    v0[r] = coarse_at(V, A.in4, s, kc * ncxy + J * ncx + I);
+    v1[r] = coarse_at(V, A.in4, s, kc * ncxy + Jp * ncx + I);
   }
   const T iHX = A.g.iHX[I], iHY = A.g.iHY[J];
-  T wv = W[K * ncxy + J * ncx + I];
+  T wv = coarse_at(W, A.in5, s, K * ncxy + J * ncx + I);
   for (int m = 0; m < mz; ++m) {
     const int k = K * mz + m;
     const T* R = A.g.Rz + (K * mz + m) * 3;
@@ -71,7 +84,7 @@ __global__ void __launch_bounds__(256) stage_z(RefArgs<T> A) {
     A.out2[k * ncxy + J * ncx + I] = wv;
     if (m < mz - 1) wv = wv - A.g.hz[k] * ((b - a) * iHX + (d - c) * iHY);
   }
-  if (K == ncz - 1) A.out2[A.nz * ncxy + J * ncx + I] = W[ncz * ncxy + J * ncx + I];
+  if (K == ncz - 1) A.out2[A.nz * ncxy + J * ncx + I] = coarse_at(W, A.in5, s, ncz * ncxy + J * ncx + I);
 }
 
 // stage y: thread per (coarse I, coarse J, dense k)
@@ -332,9 +345,11 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
   return e;
 }
 
+// U1/V1/W1 null: refine (U, V, W); otherwise refine (1 - frac) (U, V, W) + frac (U1, V1, W1).
 template <typename T>
 hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, const void* W,
-                    void* u, void* v, void* w, hipStream_t s) {
+                    const void* U1, const void* V1, const void* W1, double frac, void* u, void* v,
+                    void* w, hipStream_t s) {
   const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
   const int64_t yc = (int64_t)c->nz * c->ny * c->ncx, yc1 = (int64_t)(c->nz + 1) * c->ny * c->ncx;
   const size_t need = sizeof(T) * (size_t)(2 * zc + zc1 + 2 * yc + yc1);
@@ -348,6 +363,8 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
   T* Wzy = Vzy + yc;
   RefArgs<T> a = ref_args<T>(c, g);
   a.in0 = (const T*)U; a.in1 = (const T*)V; a.in2 = (const T*)W;
+  a.in3 = (const T*)U1; a.in4 = (const T*)V1; a.in5 = (const T*)W1;
+  a.s = (T)frac;
   a.out0 = Uz; a.out1 = Vz; a.out2 = Wz;
   hipLaunchKernelGGL(stage_z<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
   a.in0 = Uz; a.in1 = Vz; a.in2 = Wz;
@@ -409,8 +426,16 @@ hipError_t refine_transpose_t(mr_ctx* c, const Geom<T>& g, const void* gu, const
 
 hipError_t launch_refine(mr_ctx* c, const void* U, const void* V, const void* W, void* u, void* v,
                          void* w, hipStream_t s) {
-  if (c->precision == MR_FP64) return refine_t<double>(c, c->g64, U, V, W, u, v, w, s);
-  return refine_t<float>(c, c->g32, U, V, W, u, v, w, s);
+  if (c->precision == MR_FP64)
+    return refine_t<double>(c, c->g64, U, V, W, nullptr, nullptr, nullptr, 0.0, u, v, w, s);
+  return refine_t<float>(c, c->g32, U, V, W, nullptr, nullptr, nullptr, 0.0, u, v, w, s);
+}
+
+hipError_t launch_refine_time(mr_ctx* c, const void* U0, const void* V0, const void* W0,
+                              const void* U1, const void* V1, const void* W1, double frac, void* u,
+                              void* v, void* w, hipStream_t s) {
+  if (c->precision == MR_FP64) return refine_t<double>(c, c->g64, U0, V0, W0, U1, V1, W1, frac, u, v, w, s);
+  return refine_t<float>(c, c->g32, U0, V0, W0, U1, V1, W1, frac, u, v, w, s);
 }
 
 hipError_t launch_refine_transpose(mr_ctx* c, const void* gu, const void* gv, const void* gw,

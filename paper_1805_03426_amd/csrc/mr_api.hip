@@ -497,6 +497,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
         s = t;
       }
     c->atot = s + comp;
+    c->vtot = c->atot * (P.z.f[P.z.n] - P.z.f[0]);
   }
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { int r = hip_fail(c, e); delete c; return r; }
@@ -609,6 +610,65 @@ int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profil
     for (double t : tmp)
       if (!std::isfinite(t)) return MR_ENONFINITE;
   }
+  return MR_OK;
+}
+
+int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, double* host_out,
+                           void* stream) {
+  if (!ctx || !theta || !dev_out) return MR_EINVAL;
+  hipStream_t s = as_stream(stream);
+  MR_LAUNCH(mr::launch_dissipation(ctx, theta, dev_out, s));
+  if (host_out) {
+    MR_LAUNCH(hipMemcpyAsync(host_out, dev_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MR_LAUNCH(hipStreamSynchronize(s));
+    for (int q = 0; q < 4; ++q)
+      if (!std::isfinite(host_out[q])) return MR_ENONFINITE;
+  }
+  return MR_OK;
+}
+
+int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, const void* W0,
+                                 const void* U1, const void* V1, const void* W1, int64_t i,
+                                 int64_t mt, void* u, void* v, void* w, void* stream) {
+  if (!ctx || !U0 || !V0 || !W0 || !U1 || !V1 || !W1 || !u || !v || !w) return MR_EINVAL;
+  if (mt < 1 || i < 0 || i > mt) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w,
+                                   as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_integrate_scalar(mr_ctx* ctx, const void* theta, void* theta_c, void* stream) {
+  if (!ctx || !theta || !theta_c || theta == theta_c) return MR_EINVAL;
+  MR_LAUNCH(mr::launch_integrate(ctx, theta, theta_c, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const void* V0,
+                   const void* W0, const void* U1, const void* V1, const void* W1, void* u, void* v,
+                   void* w, void* const* ring, int32_t* prev, int32_t* cur, void* theta_c,
+                   void* stream) {
+  if (!ctx || n0 < 0 || mt < 1 || !U0 || !V0 || !W0 || !U1 || !V1 || !W1 || !u || !v || !w)
+    return MR_EINVAL;
+  if (!ring || !prev || !cur) return MR_EINVAL;
+  int p = *prev, c = *cur;
+  if (c < 0 || c > 2 || (n0 > 0 && (p < 0 || p > 2 || p == c))) return MR_EINVAL;
+  if (!ring[0] || !ring[1] || !ring[2] || ring[0] == ring[1] || ring[0] == ring[2] ||
+      ring[1] == ring[2])
+    return MR_EINVAL;
+  if (n0 == 0) p = c;
+  hipStream_t s = as_stream(stream);
+  for (int32_t i = 1; i <= mt; ++i) {
+    MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
+    const int64_t n = n0 + i - 1;
+    int o = 0;
+    while (o == c || o == p) ++o;   // the buffer holding neither level
+    MR_LAUNCH(mr::launch_step(ctx, n, ring[p], ring[c], ring[o], u, v, w, s));
+    p = c;
+    c = o;
+  }
+  if (theta_c) MR_LAUNCH(mr::launch_integrate(ctx, ring[c], theta_c, s));
+  *prev = p;
+  *cur = c;
   return MR_OK;
 }
 

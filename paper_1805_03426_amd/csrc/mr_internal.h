@@ -68,6 +68,7 @@ struct mr_ctx {
   int last_err;
   int L, nch;                      // z chunk length and count of the line solver
   double atot;                     // total horizontal area
+  double vtot;                     // domain volume (atot times the height)
   double tau[mr::NKINDS];
   void* tables;                    // one device block with every table
   mr::Geom<double> g64;
@@ -105,6 +106,39 @@ hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void
                              hipStream_t s);
 hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, int64_t nbytes, hipStream_t s);
+hipError_t launch_refine_time(mr_ctx* c, const void* U0, const void* V0, const void* W0,
+                              const void* U1, const void* V1, const void* W1, double frac, void* u,
+                              void* v, void* w, hipStream_t s);
+hipError_t launch_integrate(mr_ctx* c, const void* th, void* tc, hipStream_t s);
+hipError_t launch_dissipation(mr_ctx* c, const void* th, double* out, hipStream_t s);
+// Grows the context's reduction scratch to at least `bytes`.
+hipError_t ensure_red(mr_ctx* c, size_t bytes);
+
+// Double-double (error-free two-sum) accumulation for compensated reductions.
+struct DD {
+  double s, c;
+};
+
+__device__ __forceinline__ DD dd_add(DD a, double b) {
+  const double t = a.s + b;
+  const double bp = t - a.s;
+  const double e = (a.s - (t - bp)) + (b - bp);
+  return {t, a.c + e};
+}
+
+__device__ __forceinline__ DD dd_merge(DD a, DD b) {
+  DD r = dd_add(a, b.s);
+  r.c += b.c;
+  return r;
+}
+
+__device__ __forceinline__ DD wave_sum(DD v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    DD o{__shfl_down(v.s, off, kWave), __shfl_down(v.c, off, kWave)};
+    v = dd_merge(v, o);
+  }
+  return v;
+}
 
 // Step-type bookkeeping shared by the host API and the launchers.
 inline int step_kind(int64_t n, int n_avg) {
