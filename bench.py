@@ -8,8 +8,11 @@ value = dense-cell updates per second over the whole job.
 
 Also reported, outside the timed region: the same workload with FP32 storage,
 the adjoint workload (FP32, 20 steps, checkpoint every 5: forward and backward
-times), the copy-kernel bandwidth, the roofline of the dominant kernel (the
-fused scalar step) and the oracle's CPU time on a bounded sample.
+times), the inter-grid kernels (integration, Nu_T, refinement in time, one
+coarse step of M_t = 4), the FP32 step kernel on the 576^3 and
+1024x1024x512 workloads, the copy-kernel bandwidth, the roofline of the
+dominant kernel (the fused scalar step) and the oracle's CPU time on a
+bounded sample.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -179,6 +182,86 @@ def adjoint_times(steps_override=None):
     return float(np.median(tf)), float(np.median(tb)), N
 
 
+def _event_ms(fn, reps=20, warmup=3):
+    """Mean time (ms) of fn() enqueued reps times on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def intergrid_times(w, mt=4):
+    """Inter-grid kernels of the workload (FP64): dense-to-coarse integration,
+    Nu_T, refinement with and without the time interpolation, and one coarse
+    step of mt scalar steps; algorithmic bytes per launch and % of HBM peak."""
+    r = Run(w, "fp64")
+    c = r.ctx
+    cells, coarse = w.cells, w.cells // (w.m[0] * w.m[1] * w.m[2])
+    ncw = coarse + c.ncx * c.ncy            # coarse W has one more level
+    dense_w = cells + c.nx * c.ny
+    U1, V1, W1 = (t.flip(0).contiguous() for t in (r.U, r.V, r.W))   # a second coarse level
+    W1[0].zero_()
+    W1[-1].zero_()
+    tc = c.empty(c.shape_coarse)
+    diss = torch.empty(4, dtype=torch.float64, device="cuda")
+    uvw = (r.u, r.v, r.w_)
+    out = {}
+
+    def rec(name, ms, nbytes):
+        out[name] = dict(ms=ms, alg_bytes=nbytes, hbm_frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+    rec("integrate_scalar", _event_ms(lambda: c.integrate_scalar(r.th0, out=tc)), 8 * (cells + coarse))
+    rec("thermal_dissipation", _event_ms(lambda: c.thermal_dissipation(r.th0, out=diss, sync=False)), 8 * cells)
+    rec("interpolate_velocity", _event_ms(lambda: c.interpolate_velocity(r.U, r.V, r.W, out=uvw)),
+        8 * (2 * coarse + ncw + 2 * cells + dense_w))
+    rec("interpolate_velocity_time",
+        _event_ms(lambda: c.interpolate_velocity_time(r.U, r.V, r.W, U1, V1, W1, 1, mt, out=uvw)),
+        8 * (2 * (2 * coarse + ncw) + 2 * cells + dense_w))
+    ring = [r.th0.clone(), c.empty(c.shape_cell), c.empty(c.shape_cell)]
+    state = {"n0": 0, "p": 0, "c": 0}
+
+    def one_coarse_step():
+        state["p"], state["c"] = c.coarse_step(state["n0"], mt, r.U, r.V, r.W, U1, V1, W1, uvw, ring,
+                                               state["p"], state["c"], tc)
+        state["n0"] += mt
+
+    ms = _event_ms(one_coarse_step, reps=5, warmup=1)
+    out["coarse_step"] = dict(mt=mt, ms=ms, dense_cell_updates_per_s=cells * mt / (ms * 1e-3))
+    c.close()
+    return out
+
+
+def large_fp32_step_times():
+    """FP32 scalar-step kernel on the 576^3 (M = 3) and 1024x1024x512 workloads:
+    mean kernel time over a few steps and % of HBM peak (24 B per dense cell)."""
+    out = {}
+    for name in ("rb576-m3-fp32", "rb1024x1024x512-m2-fp32"):
+        w = WORKLOADS[name]
+        r = Run(w, "fp32")
+        c = r.ctx
+        c.interpolate_velocity(r.U, r.V, r.W, out=(r.u, r.v, r.w_))
+        state = {"n": 0, "prev": 0, "cur": 0}
+
+        def step():
+            n, out = state["n"], 1 + state["n"] % 3   # ring[0] holds theta^0
+            r.runner.step(n, state["prev"], state["cur"], out)
+            state.update(n=n + 1, prev=state["cur"], cur=out)
+
+        ms = _event_ms(step, reps=10, warmup=2)
+        out[name] = dict(step_kernel_ms=ms, dense_cell_updates_per_s=w.cells / (ms * 1e-3),
+                         step_hbm_frac_alg=24 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        c.close()
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle's FP64 scalar step on the same workload, a bounded sample:
     as many whole-field steps as fit in the budget (at least one)."""
@@ -251,6 +334,11 @@ def main():
         extras["adjoint"] = dict(workload=ADJOINT_WORKLOAD, steps=nad, forward_s=tf, backward_s=tb,
                                  backward_over_forward=tb / tf)
         torch.cuda.empty_cache()
+        print("bench: inter-grid kernels", file=sys.stderr, flush=True)
+        extras["intergrid"] = intergrid_times(w)
+        torch.cuda.empty_cache()
+        print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
+        extras["fp32_large"] = large_fp32_step_times()
         extras["copy_bandwidth_GBs"] = copy_bandwidth()
 
     if args.copy_probe:
