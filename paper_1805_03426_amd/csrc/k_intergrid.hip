@@ -11,9 +11,9 @@
 //
 // Dissipation: every dense cell owns its low x face, low y face and low z face
 // (and the top plate for the last level); each face adds its squared
-// difference quotient times its dual volume.  Two-pass, fixed partition and
-// fixed combining order with double-double partial sums, so the result is
-// compensated and bitwise reproducible.
+// difference quotient times its dual volume.  Two-pass, fixed partition
+// (row segments x level ranges) and fixed combining order with double-double
+// partial sums, so the result is compensated and bitwise reproducible.
 #include <algorithm>
 
 #include "mr_internal.h"
@@ -64,41 +64,55 @@ __global__ void __launch_bounds__(kIntBlock) integrate_kernel(const T* th, T* tc
   }
 }
 
-constexpr int kDissBlocks = 2048;
+// Nu_T partials: a workgroup of 256 lanes covers 256 consecutive columns of
+// one row j and a range of kb levels; each lane walks up its column carrying
+// theta(k-1), reads its own value, its x neighbour (mostly the same cache
+// lines) and the row j-1 value, and accumulates the faces on the low side of
+// its cell (plus the top plate for the last level).  Fixed partition:
+// part[b] holds workgroup b's three double-double sums.
+constexpr int kDissMaxParts = 8192;
 
 template <typename T>
 __global__ void __launch_bounds__(256) diss_partial(const T* th, const double* hx, const double* hy,
                                                     const double* hz, const double* idxc,
                                                     const double* idyc, const double* dcz, int nx,
-                                                    int ny, int nz, int dir_bot, int dir_top,
-                                                    double t_bot, double t_top, double* part) {
+                                                    int ny, int nz, int nbx, int kb, int dir_bot,
+                                                    int dir_top, double t_bot, double t_top,
+                                                    double* part) {
   __shared__ DD sh[3][256 / kWave];
-  const int nxy = nx * ny;
-  const int64_t cells = (int64_t)nxy * nz;
+  const int b = blockIdx.x;
+  const int bx = b % nbx, j = (b / nbx) % ny, kc = b / (nbx * ny);
+  const int i_raw = bx * 256 + threadIdx.x;
+  const bool on = i_raw < nx;
+  const int i = on ? i_raw : nx - 1;
+  const int im = i == 0 ? nx - 1 : i - 1;
+  const int jm = j == 0 ? ny - 1 : j - 1;
+  const size_t nxy = (size_t)nx * ny;
+  const int k0 = kc * kb, k1 = min(nz, k0 + kb);
+  const double wx = idxc[i] * hy[j], wy = idyc[j] * hx[i], area = hx[i] * hy[j];
   DD sx{0.0, 0.0}, sy{0.0, 0.0}, sz{0.0, 0.0};
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cells;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % nx), j = (int)((q / nx) % ny), k = (int)(q / nxy);
-    const int im = i == 0 ? nx - 1 : i - 1;
-    const int jm = j == 0 ? ny - 1 : j - 1;
-    const int row = k * nxy + j * nx;
-    const double c = th[row + i];
-    const double dx = c - (double)th[row + im];
-    const double dy = c - (double)th[k * nxy + jm * nx + i];
-    sx = dd_add(sx, dx * dx * idxc[i] * (hy[j] * hz[k]));
-    sy = dd_add(sy, dy * dy * idyc[j] * (hx[i] * hz[k]));
-    const double area = hx[i] * hy[j];
-    if (k > 0) {
-      const double dz = c - (double)th[row - nxy + i];
-      sz = dd_add(sz, dz * dz / dcz[k] * area);
-    } else if (dir_bot) {
-      const double dz = c - t_bot;
-      sz = dd_add(sz, dz * dz / dcz[0] * area);
+  double below = k0 > 0 ? (double)th[(size_t)(k0 - 1) * nxy + (size_t)j * nx + i] : 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const T* lvl = th + (size_t)k * nxy;
+    const double c = lvl[(size_t)j * nx + i];
+    const double dx = c - (double)lvl[(size_t)j * nx + im];
+    const double dy = c - (double)lvl[(size_t)jm * nx + i];
+    if (on) {
+      sx = dd_add(sx, dx * dx * wx * hz[k]);
+      sy = dd_add(sy, dy * dy * wy * hz[k]);
+      if (k > 0) {
+        const double dz = c - below;
+        sz = dd_add(sz, dz * dz / dcz[k] * area);
+      } else if (dir_bot) {
+        const double dz = c - t_bot;
+        sz = dd_add(sz, dz * dz / dcz[0] * area);
+      }
+      if (k == nz - 1 && dir_top) {
+        const double dz = t_top - c;
+        sz = dd_add(sz, dz * dz / dcz[nz] * area);
+      }
     }
-    if (k == nz - 1 && dir_top) {
-      const double dz = t_top - c;
-      sz = dd_add(sz, dz * dz / dcz[nz] * area);
-    }
+    below = c;
   }
   sx = wave_sum(sx);
   sy = wave_sum(sy);
@@ -116,7 +130,7 @@ __global__ void __launch_bounds__(256) diss_partial(const T* th, const double* h
       sy = dd_merge(sy, sh[1][p]);
       sz = dd_merge(sz, sh[2][p]);
     }
-    double* o = part + (size_t)blockIdx.x * 6;
+    double* o = part + (size_t)b * 6;
     o[0] = sx.s; o[1] = sx.c;
     o[2] = sy.s; o[3] = sy.c;
     o[4] = sz.s; o[5] = sz.c;
@@ -166,21 +180,27 @@ hipError_t launch_integrate(mr_ctx* c, const void* th, void* tc, hipStream_t s) 
 }
 
 hipError_t launch_dissipation(mr_ctx* c, const void* th, double* out, hipStream_t s) {
-  const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
-  const int nb = (int)std::min<int64_t>(kDissBlocks, (cells + 255) / 256);
-  hipError_t e = ensure_red(c, sizeof(double) * 6 * kDissBlocks);
+  const int nbx = (c->nx + 255) / 256;
+  const int64_t rows = (int64_t)nbx * c->ny;
+  // levels per workgroup: enough workgroups to fill the chip, at most kDissMaxParts partials
+  int nkb = (int)std::max<int64_t>(1, std::min<int64_t>(c->nz, kDissMaxParts / std::max<int64_t>(1, rows)));
+  const int kb = (c->nz + nkb - 1) / nkb;
+  nkb = (c->nz + kb - 1) / kb;
+  const int64_t nb = rows * nkb;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipError_t e = ensure_red(c, sizeof(double) * 6 * (size_t)nb);
   if (e != hipSuccess) return e;
   const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
   const Geom<double>& g = c->g64;
   if (c->precision == MR_FP64)
-    hipLaunchKernelGGL(diss_partial<double>, dim3(nb), dim3(256), 0, s, (const double*)th, c->hx64,
-                       c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, db, dtp,
-                       c->t_bot, c->t_top, c->red);
+    hipLaunchKernelGGL(diss_partial<double>, dim3((unsigned)nb), dim3(256), 0, s, (const double*)th,
+                       c->hx64, c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, nbx,
+                       kb, db, dtp, c->t_bot, c->t_top, c->red);
   else
-    hipLaunchKernelGGL(diss_partial<float>, dim3(nb), dim3(256), 0, s, (const float*)th, c->hx64,
-                       c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, db, dtp,
-                       c->t_bot, c->t_top, c->red);
-  hipLaunchKernelGGL(diss_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, nb, c->vtot,
+    hipLaunchKernelGGL(diss_partial<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float*)th,
+                       c->hx64, c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, nbx,
+                       kb, db, dtp, c->t_bot, c->t_top, c->red);
+  hipLaunchKernelGGL(diss_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, (int)nb, c->vtot,
                      c->kappa * sqrt(c->ra * c->pr), out);
   return hipGetLastError();
 }

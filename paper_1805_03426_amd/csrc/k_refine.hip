@@ -1,17 +1,21 @@
 // Divergence-free coarse -> dense refinement of the staggered velocity
 // (paper Sec. 3.2, Fig. 5a, Eqs. 12-19) and its transpose.
 //
-// Three stage kernels, z then y then x.  In each stage one thread owns one
-// coarse cell along the refined axis: it splits the two pairs of outer normal
-// face velocities of its column with R (Eq. 19, three-cell stencil) and marches
-// the inner faces of the refined axis upward from the coarse face below,
-// each from zero net outward flux of the sub-cell under it.  Intermediate
-// fields (after z, after z and y) are kept in a context-owned buffer.
+// Stages z, then y, then x.  In each stage one coarse cell along the refined
+// axis splits the two pairs of outer normal face velocities of its column with
+// R (Eq. 19, three-cell stencil) and marches the inner faces of the refined
+// axis upward from the coarse face below, each from zero net outward flux of
+// the sub-cell under it.  The forward refinement runs the three stages in one
+// kernel with the intermediates in LDS (refine_fused); the three separate
+// stage kernels, with the intermediates in a context-owned buffer, serve the
+// shapes it does not cover (mz > 4 or a tile beyond its LDS budget).
 //
 // The transpose runs the stages in reverse order; a march becomes a suffix
 // sum inside each coarse cell, a split an R^T gather (no atomics: every output
 // value is written by exactly one thread, in a fixed order).
 #include <string.h>
+
+#include <algorithm>
 
 #include "mr_internal.h"
 
@@ -152,6 +156,261 @@ __global__ void __launch_bounds__(256) stage_x(RefArgs<T> A) {
     A.out2[k * nxy + j * nx + i] = c;
     if (k == nz - 1) A.out2[nz * nxy + j * nx + i] = d;
     if (m < mx - 1) uu = uu - A.g.hx[i] * ((b - a) * ihy + (d - c) * ihz);
+  }
+}
+
+// ------------------------------------------------------------ fused forward
+// The three stages in one kernel.  A workgroup owns TI coarse columns
+// [I0, I0+TI) (TI*mx <= 64 dense columns) of TJ coarse rows [J0, J0+TJ) and a
+// range of coarse layers, walked one layer K at a time:
+//   Z: for halo columns I0-1 .. I0+TI+1 and rows J0-1 .. J0+TJ, split U, V
+//      along z and march W (as stage_z), into LDS.  The coarse values of
+//      layer K+1 are loaded into registers while layer K is refined;
+//   Y: for the layer's dense levels, the tile's rows and halo columns
+//      I0-1 .. I0+TI, split the z-refined U, W along y and march V (as
+//      stage_y), into LDS;
+//   X: for the tile's dense cells, split V, W along x; each lane runs the x
+//      march of U up to its own sub-column (the same operations in the same
+//      order as stage_x).
+// Each dense value is written once, 64 consecutive columns per row; the only
+// HBM reads are the coarse levels (cache-resident halo re-reads).  x and y
+// are periodic, so the y stencil of row J is rows J-1 .. J+1.
+constexpr int kFuseCols = 64;
+
+__device__ __forceinline__ int wrapm(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+constexpr int kFuseMaxMz = 4;   // z refinement factors the fused kernel is built for
+
+// The raw coarse values (both time levels) one stage-z item reads for one layer.
+template <typename T, bool BLEND>
+struct ZLoad {
+  T u0[3], u1[3], v0[3], v1[3], wb, wt;
+  T u0b[BLEND ? 3 : 1], u1b[BLEND ? 3 : 1], v0b[BLEND ? 3 : 1], v1b[BLEND ? 3 : 1], wbb, wtb;
+};
+
+template <typename T, bool BLEND>
+__device__ __forceinline__ void z_load(const RefArgs<T>& A, int K, int Ig, int Ip, int Jg, int Jp,
+                                       ZLoad<T, BLEND>& z) {
+  const int ncx = A.ncx, ncxy = A.ncx * A.ncy, mz = A.mz;
+  for (int q = 0; q < 3; ++q) {
+    const int kc3 = A.g.sz[K * 3 + q];
+    z.u0[q] = A.in0[kc3 * ncxy + Jg * ncx + Ig];
+    z.u1[q] = A.in0[kc3 * ncxy + Jg * ncx + Ip];
+    z.v0[q] = A.in1[kc3 * ncxy + Jg * ncx + Ig];
+    z.v1[q] = A.in1[kc3 * ncxy + Jp * ncx + Ig];
+    if constexpr (BLEND) {
+      z.u0b[q] = A.in3[kc3 * ncxy + Jg * ncx + Ig];
+      z.u1b[q] = A.in3[kc3 * ncxy + Jg * ncx + Ip];
+      z.v0b[q] = A.in4[kc3 * ncxy + Jg * ncx + Ig];
+      z.v1b[q] = A.in4[kc3 * ncxy + Jp * ncx + Ig];
+    }
+  }
+  z.wb = A.in2[K * ncxy + Jg * ncx + Ig];
+  z.wt = A.in2[(K + 1) * ncxy + Jg * ncx + Ig];
+  if constexpr (BLEND) {
+    z.wbb = A.in5[K * ncxy + Jg * ncx + Ig];
+    z.wtb = A.in5[(K + 1) * ncxy + Jg * ncx + Ig];
+  }
+}
+
+// Per-layer z tables in LDS, one slot per layer parity: R_z rows, hz, 1/hz.
+constexpr int kZTab = 5 * kFuseMaxMz;
+
+// The table value lane t contributes for layer K (lanes t < 5 mz).
+template <typename T>
+__device__ __forceinline__ T ztab_load(const Geom<T>& g, int K, int mz, int t) {
+  if (t < 3 * mz) return g.Rz[(K * mz + t / 3) * 3 + t % 3];
+  if (t < 4 * mz) return g.hz[K * mz + t - 3 * mz];
+  if (t < 5 * mz) return g.ihz[K * mz + t - 4 * mz];
+  return T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void ztab_store(T* slot, int mz, int t, T v) {
+  if (t < 3 * mz) slot[t] = v;                                   // rz[m][r] at 3 m + r
+  else if (t < 4 * mz) slot[3 * kFuseMaxMz + t - 3 * mz] = v;    // hz[m]
+  else if (t < 5 * mz) slot[4 * kFuseMaxMz + t - 4 * mz] = v;    // 1/hz[m]
+}
+
+template <typename T, bool BLEND>
+__device__ __forceinline__ T zb(T a, T b, T s) {
+  if constexpr (BLEND) return (T(1) - s) * a + s * b;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T rdot3(const T* R, const T q[3]) {
+  return R[0] * q[0] + R[1] * q[1] + R[2] * q[2];
+}
+
+// LDS element counts of refine_fused (tables first, then the stage fields).
+__host__ __device__ inline int fused_tables(int TI, int TJ, int mx, int my) {
+  const int NXH = TI + 3, RY = TJ * my, CX = TI * mx;
+  return NXH + 5 * RY + 4 * CX + 2 * kZTab;
+}
+__host__ __device__ inline int fused_fields(int TI, int TJ, int my, int mz) {
+  const int NXH = TI + 3, NYH = TJ + 2, RY = TJ * my;
+  return 2 * mz * NYH * NXH + (mz + 1) * NYH * NXH + mz * RY * NXH + (mz + 1) * RY * NXH +
+         mz * TJ * (my + 1) * NXH;
+}
+
+template <typename T, bool BLEND>
+__global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ, int nbx, int nby,
+                                                    int KC) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* const sm = reinterpret_cast<T*>(smem_raw);
+  const int ncx = A.ncx, ncy = A.ncy, ncz = A.ncz, mx = A.mx, my = A.my, mz = A.mz;
+  const int nx = A.nx, nz = A.nz;
+  const int nxy = nx * A.ny;
+  const int NXH = TI + 3, NYH = TJ + 2, RY = TJ * my, CX = TI * mx;
+  // per-workgroup tables
+  T* const tIHX = sm;                          // [NXH] 1/HX of the halo columns
+  T* const tRy = tIHX + NXH;                   // [RY][3]
+  T* const tHy = tRy + 3 * RY;                 // [RY]
+  T* const tIhy = tHy + RY;                    // [RY]
+  T* const tRx = tIhy + RY;                    // [CX][3]
+  T* const tHx = tRx + 3 * CX;                 // [CX]
+  T* const tZ = tHx + CX;                      // [2][kZTab] per-layer z tables, by layer parity
+  // stage fields
+  T* const Uz = tZ + 2 * kZTab;                // [mz][NYH][NXH]
+  T* const Vz = Uz + mz * NYH * NXH;           // [mz][NYH][NXH]
+  T* const Wz = Vz + mz * NYH * NXH;           // [mz+1][NYH][NXH]
+  T* const Uzy = Wz + (mz + 1) * NYH * NXH;    // [mz][RY][NXH]
+  T* const Wzy = Uzy + mz * RY * NXH;          // [mz+1][RY][NXH]
+  T* const Vzy = Wzy + (mz + 1) * RY * NXH;    // [mz][TJ][my+1][NXH]
+  const int b = blockIdx.x;
+  const int bx = b % nbx, by = (b / nbx) % nby, kc = b / (nbx * nby);
+  const int I0 = bx * TI, J0 = by * TJ;
+  const int TJv = min(TJ, ncy - J0);           // rows of this tile
+  const int K0 = kc * KC, K1 = min(ncz, K0 + KC);
+  const int t = threadIdx.x;
+  const T s = A.s;
+  const Geom<T>& g = A.g;
+
+  for (int e = t; e < NXH; e += blockDim.x) tIHX[e] = g.iHX[wrapm(I0 - 1 + e, ncx)];
+  for (int e = t; e < TJv * my; e += blockDim.x) {
+    const int j = J0 * my + e;
+    for (int r = 0; r < 3; ++r) tRy[3 * e + r] = g.Ry[j * 3 + r];
+    tHy[e] = g.hy[j];
+    tIhy[e] = g.ihy[j];
+  }
+  for (int e = t; e < CX; e += blockDim.x) {
+    const int i = min(I0 * mx + e, nx - 1);
+    for (int r = 0; r < 3; ++r) tRx[3 * e + r] = g.Rx[i * 3 + r];
+    tHx[e] = g.hx[i];
+  }
+
+  // stage-z item of this thread: halo row zr, halo column zl
+  const bool zon = t < NYH * NXH;
+  const int zr = zon ? t / NXH : 0, zl = zon ? t - zr * NXH : 0;
+  const int zI = wrapm(I0 - 1 + zl, ncx), zIp = wrapm(zI + 1, ncx);
+  const int zJ = wrapm(J0 - 1 + zr, ncy), zJp = wrapm(zJ + 1, ncy);
+  const T ziHX = g.iHX[zI], ziHY = g.iHY[zJ];
+  // stage-x lane roles: column col of the tile, sub-column sub of coarse column Ix
+  const int col = t % kFuseCols, grp = t / kFuseCols;
+  const int Ix = I0 + col / mx, sub = col - (col / mx) * mx;
+  const bool xon = col < CX && Ix < ncx;
+  int xloc[3];
+  for (int r = 0; r < 3; ++r) xloc[r] = xon ? wrapm(g.sx[Ix * 3 + r] - (I0 - 1), ncx) : 0;
+
+  ZLoad<T, BLEND> cur, nxt;
+  if (zon && K0 < K1) z_load<T, BLEND>(A, K0, zI, zIp, zJ, zJp, cur);
+  if (K0 < K1) ztab_store(tZ + (K0 & 1) * kZTab, mz, t, ztab_load(g, K0, mz, t));
+  __syncthreads();   // tables
+  for (int K = K0; K < K1; ++K) {
+    // the next layer's coarse values and z tables, in flight while this one is refined
+    if (zon && K + 1 < K1) z_load<T, BLEND>(A, K + 1, zI, zIp, zJ, zJp, nxt);
+    const T tnext = K + 1 < K1 ? ztab_load(g, K + 1, mz, t) : T(0);
+    const T* const zt = tZ + (K & 1) * kZTab;
+    const T* const ihzK = zt + 4 * kFuseMaxMz;
+    // ---- Z
+    if (zon) {
+      T u0[3], u1[3], v0[3], v1[3];
+      for (int q = 0; q < 3; ++q) {
+        u0[q] = zb<T, BLEND>(cur.u0[q], cur.u0b[BLEND ? q : 0], s);
+        u1[q] = zb<T, BLEND>(cur.u1[q], cur.u1b[BLEND ? q : 0], s);
+        v0[q] = zb<T, BLEND>(cur.v0[q], cur.v0b[BLEND ? q : 0], s);
+        v1[q] = zb<T, BLEND>(cur.v1[q], cur.v1b[BLEND ? q : 0], s);
+      }
+      T wv = zb<T, BLEND>(cur.wb, cur.wbb, s);
+      for (int m = 0; m < mz; ++m) {
+        const T* R = zt + 3 * m;
+        const T a = rdot3(R, u0), bb = rdot3(R, u1), c = rdot3(R, v0), d = rdot3(R, v1);
+        Uz[(m * NYH + zr) * NXH + zl] = a;
+        Vz[(m * NYH + zr) * NXH + zl] = c;
+        Wz[(m * NYH + zr) * NXH + zl] = wv;
+        if (m < mz - 1) wv = wv - zt[3 * kFuseMaxMz + m] * ((bb - a) * ziHX + (d - c) * ziHY);
+      }
+      Wz[(mz * NYH + zr) * NXH + zl] = zb<T, BLEND>(cur.wt, cur.wtb, s);
+    }
+    __syncthreads();
+    // ---- Y: items (tile row jt, level m, halo column l)
+    const int ny_items = TJv * mz * (NXH - 1);
+    for (int it = t; it < ny_items; it += blockDim.x) {
+      const int l = it % (NXH - 1), rest = it / (NXH - 1);
+      const int m = rest % mz, jt = rest / mz;
+      T u0[3], u1[3], w0[3], w1[3];
+      for (int r = 0; r < 3; ++r) {
+        u0[r] = Uz[(m * NYH + jt + r) * NXH + l];
+        u1[r] = Uz[(m * NYH + jt + r) * NXH + l + 1];
+        w0[r] = Wz[(m * NYH + jt + r) * NXH + l];
+        w1[r] = Wz[((m + 1) * NYH + jt + r) * NXH + l];
+      }
+      const T iHX = tIHX[l], ihz = ihzK[m];
+      T vv = Vz[(m * NYH + jt + 1) * NXH + l];
+      for (int q = 0; q < my; ++q) {
+        const int row = jt * my + q;
+        const T* R = tRy + 3 * row;
+        const T a = rdot3(R, u0), bb = rdot3(R, u1), c = rdot3(R, w0), d = rdot3(R, w1);
+        Uzy[(m * RY + row) * NXH + l] = a;
+        if (l == NXH - 2) Uzy[(m * RY + row) * NXH + l + 1] = bb;
+        Vzy[((m * TJ + jt) * (my + 1) + q) * NXH + l] = vv;
+        Wzy[(m * RY + row) * NXH + l] = c;
+        if (m == mz - 1) Wzy[(mz * RY + row) * NXH + l] = d;
+        if (q < my - 1) vv = vv - tHy[row] * ((bb - a) * iHX + (d - c) * ihz);
+      }
+      Vzy[((m * TJ + jt) * (my + 1) + my) * NXH + l] = Vz[(m * NYH + jt + 2) * NXH + l];
+    }
+    // publish the next layer's z tables into the other parity slot: its last
+    // readers (stage z and x of layer K-1) are behind the barrier after stage z
+    if (K + 1 < K1) ztab_store(tZ + ((K + 1) & 1) * kZTab, mz, t, tnext);
+    __syncthreads();
+    // ---- X: items (dense row of the tile, level m) x 64 columns.  The next
+    // layer's stage z writes only Uz, Vz, Wz, which stage x does not read, and
+    // its tables sit in the other parity slot, so no barrier is needed after it.
+    const int npairs = TJv * my * mz;
+    for (int pr = grp; pr < npairs; pr += 4) {
+      if (!xon) continue;
+      const int m = pr % mz, row = pr / mz;
+      const int jt = row / my, q = row - jt * my;
+      const int i = Ix * mx + sub, j = (J0 + jt) * my + q, k = K * mz + m;
+      T v0[3], v1[3], w0[3], w1[3];
+      for (int r = 0; r < 3; ++r) {
+        v0[r] = Vzy[((m * TJ + jt) * (my + 1) + q) * NXH + xloc[r]];
+        v1[r] = Vzy[((m * TJ + jt) * (my + 1) + q + 1) * NXH + xloc[r]];
+        w0[r] = Wzy[(m * RY + row) * NXH + xloc[r]];
+        w1[r] = Wzy[((m + 1) * RY + row) * NXH + xloc[r]];
+      }
+      const T ihy = tIhy[row], ihz = ihzK[m];
+      // the x march up to this sub-column, in the order of stage_x
+      T uu = Uzy[(m * RY + row) * NXH + (col / mx) + 1];
+      for (int mp = 0; mp < sub; ++mp) {
+        const T* Rp = tRx + 3 * (col - sub + mp);
+        const T ap = rdot3(Rp, v0), bp = rdot3(Rp, v1), cp = rdot3(Rp, w0), dp = rdot3(Rp, w1);
+        uu = uu - tHx[col - sub + mp] * ((bp - ap) * ihy + (dp - cp) * ihz);
+      }
+      const T* R = tRx + 3 * col;
+      const T a = rdot3(R, v0), c = rdot3(R, w0);
+      const int o = k * nxy + j * nx + i;
+      A.out0[o] = uu;
+      A.out1[o] = a;
+      A.out2[o] = c;
+      if (k == nz - 1) A.out2[o + nxy] = rdot3(R, w1);
+    }
+    cur = nxt;
   }
 }
 
@@ -346,10 +605,55 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
 }
 
 // U1/V1/W1 null: refine (U, V, W); otherwise refine (1 - frac) (U, V, W) + frac (U1, V1, W1).
+#ifndef MR_FUSED_REFINE
+#define MR_FUSED_REFINE 1
+#endif
+#ifndef MR_FUSED_ROWS
+#define MR_FUSED_ROWS 4
+#endif
+#ifndef MR_FUSED_WGS
+#define MR_FUSED_WGS 8192
+#endif
+constexpr size_t kFuseMaxLds = 64 * 1024;
+
+// LDS bytes of refine_fused for a tile of TI x TJ coarse cells.
+template <typename T>
+size_t fused_lds(int TI, int TJ, int mx, int my, int mz) {
+  return sizeof(T) * (size_t)(fused_tables(TI, TJ, mx, my) + fused_fields(TI, TJ, my, mz));
+}
+
 template <typename T>
 hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, const void* W,
                     const void* U1, const void* V1, const void* W1, double frac, void* u, void* v,
                     void* w, hipStream_t s) {
+  const int TI = kFuseCols / c->mx;
+  int TJ = 0;
+  if (TI >= 1 && c->mz <= kFuseMaxMz) {
+    // rows per tile: every stage-z item (one per halo column and row) on its own lane
+    TJ = std::min(std::min(MR_FUSED_ROWS, 256 / (TI + 3) - 2), c->ncy);
+    while (TJ >= 1 && fused_lds<T>(TI, TJ, c->mx, c->my, c->mz) > kFuseMaxLds) --TJ;
+  }
+  if (MR_FUSED_REFINE && TJ >= 1) {
+    RefArgs<T> a = ref_args<T>(c, g);
+    a.in0 = (const T*)U; a.in1 = (const T*)V; a.in2 = (const T*)W;
+    a.in3 = (const T*)U1; a.in4 = (const T*)V1; a.in5 = (const T*)W1;
+    a.s = (T)frac;
+    a.out0 = (T*)u; a.out1 = (T*)v; a.out2 = (T*)w;
+    const int nbx = (c->ncx + TI - 1) / TI, nby = (c->ncy + TJ - 1) / TJ;
+    const int64_t tiles = (int64_t)nbx * nby;
+    // coarse layers per workgroup: enough workgroups to fill the chip
+    int nkc = (int)std::max<int64_t>(1, std::min<int64_t>(c->ncz, (MR_FUSED_WGS + tiles - 1) / tiles));
+    const int KC = (c->ncz + nkc - 1) / nkc;
+    nkc = (c->ncz + KC - 1) / KC;
+    const int64_t nb = tiles * nkc;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    const size_t lds = fused_lds<T>(TI, TJ, c->mx, c->my, c->mz);
+    if (U1)
+      hipLaunchKernelGGL((refine_fused<T, true>), dim3((unsigned)nb), dim3(256), lds, s, a, TI, TJ, nbx, nby, KC);
+    else
+      hipLaunchKernelGGL((refine_fused<T, false>), dim3((unsigned)nb), dim3(256), lds, s, a, TI, TJ, nbx, nby, KC);
+    return hipGetLastError();
+  }
   const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
   const int64_t yc = (int64_t)c->nz * c->ny * c->ncx, yc1 = (int64_t)(c->nz + 1) * c->ny * c->ncx;
   const size_t need = sizeof(T) * (size_t)(2 * zc + zc1 + 2 * yc + yc1);
