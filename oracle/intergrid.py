@@ -84,7 +84,8 @@ def thermal_dissipation(g, p, th):
     x faces ((theta_i - theta_{i-1}) / dcx_i)^2 * dcx_i * hy * hz (periodic),
     y faces likewise, z faces ((theta_k - theta_{k-1}) / dcz_k)^2 * dcz_k * hx * hy
     for 0 < k < nz, and at a Dirichlet plate the difference to the wall value
-    over half a cell.  Returns dict(nu_t, gx2, gy2, gz2) with g*2 the volume
+    over half a cell; a side wall (walled x or y) adds nothing.  Returns
+    dict(nu_t, gx2, gy2, gz2) with g*2 the volume
     means of the three squared components; sums are exact-rounded (fsum)."""
     th = np.asarray(th, dtype=np.float64)
     x, y, z = g.x, g.y, g.z
@@ -92,10 +93,18 @@ def thermal_dissipation(g, p, th):
     hx = x.h[None, None, :]
     hy = y.h[None, :, None]
     hz = z.h[:, None, None]
-    dx = th - np.roll(th, 1, axis=2)                     # x face i: cells i-1, i
-    dy = th - np.roll(th, 1, axis=1)
-    ex = dx * dx / x.dc[None, None, :] * hy * hz
-    ey = dy * dy / y.dc[None, :, None] * hx * hz
+    if x.periodic:
+        dx = th - np.roll(th, 1, axis=2)                 # x face i: cells i-1, i
+        ex = dx * dx / x.dc[None, None, :] * hy * hz
+    else:                                                # interior faces 1..nx-1; walls add nothing
+        dx = th[:, :, 1:] - th[:, :, :-1]
+        ex = dx * dx / x.dc[None, None, 1:-1] * hy * hz
+    if y.periodic:
+        dy = th - np.roll(th, 1, axis=1)
+        ey = dy * dy / y.dc[None, :, None] * hx * hz
+    else:
+        dy = th[:, 1:, :] - th[:, :-1, :]
+        ey = dy * dy / y.dc[None, 1:-1, None] * hx * hz
     area = g.area_xy()
     terms_z = []
     for k in range(1, nz):

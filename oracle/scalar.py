@@ -14,12 +14,15 @@ Readings (each also listed in the design notes):
   part; the averaging step produces theta^{n+1} when (n+1) mod N_p = 0, n >= 1,
   with its diffusion on level n-1 as written in Eq. 7;
 * z walls: Dirichlet (wall value at half a cell from the first centre) or
-  adiabatic; x and y periodic;
+  adiabatic; x and y periodic, or bounded by adiabatic no-slip side walls (the
+  paper's cube, Sec. 4): a wall face carries neither advective nor diffusive
+  flux;
 * Nu(z) lives on the dense z faces; the plates use the half-cell gradient;
   Nu_paper is the mean over the interior faces, Nu_vol the height-weighted sum.
 
 Array conventions: theta (nz, ny, nx); u (nz, ny, nx) on x-faces i (between
-cells i-1 and i, periodic); v likewise on y-faces; w (nz+1, ny, nx) on z-faces.
+cells i-1 and i, periodic), or (nz, ny, nx+1) with the two wall faces when x
+is walled; v likewise on y-faces; w (nz+1, ny, nx) on z-faces.
 Test infrastructure only; all arithmetic float64, plain NumPy.
 """
 import math
@@ -61,6 +64,46 @@ def step_kind(n, n_avg, dt):
     return 2.0 * dt, 1.0, 0.0, "leapfrog"
 
 
+# ------------------------------------------------------------------ faces
+def _sides(q, axis, periodic):
+    """Cell values on the low and high side of every face normal to ``axis``:
+    periodic, face i lies between cells i-1 and i (n faces); walled, faces
+    0..n with the two wall faces seeing the adjacent cell on both sides."""
+    if periodic:
+        return np.roll(q, 1, axis=axis), q
+    q0 = np.moveaxis(q, axis, 0)
+    lo = np.concatenate([q0[:1], q0])
+    hi = np.concatenate([q0, q0[-1:]])
+    return np.moveaxis(lo, 0, axis), np.moveaxis(hi, 0, axis)
+
+
+def _open(f, axis, periodic):
+    """Face array with the wall faces (walled axis) set to zero."""
+    if periodic:
+        return f
+    f = np.array(f, dtype=np.float64, copy=True)
+    f0 = np.moveaxis(f, axis, 0)
+    f0[0] = 0.0
+    f0[-1] = 0.0
+    return f
+
+
+def _net(f, axis, periodic):
+    """f[i+1] - f[i] for every cell i from face values (outflow minus inflow)."""
+    if periodic:
+        return np.roll(f, -1, axis=axis) - f
+    return np.diff(f, axis=axis)
+
+
+def _to_cells(s_lo, s_hi, axis, periodic):
+    """Per-cell sums of face contributions: cell i receives s_hi of its low
+    face and s_lo of its high face."""
+    if periodic:
+        return s_hi + np.roll(s_lo, -1, axis=axis)
+    n = s_lo.shape[axis] - 1
+    return np.take(s_hi, np.arange(n), axis=axis) + np.take(s_lo, np.arange(1, n + 1), axis=axis)
+
+
 # ------------------------------------------------------------------ operators
 def _areas(g):
     ax = g.y.h[None, :, None] * g.z.h[:, None, None]       # x-face areas hy*hz
@@ -71,23 +114,38 @@ def _areas(g):
 
 def advection(g, th, u, v, w):
     """C(theta) = -(1/V) sum of outward fluxes u_f A_f theta_f, theta_f = mean of the
-    two cells (Eq. 5, convective term); no flux through the z walls."""
+    two cells (Eq. 5, convective term); no flux through any wall."""
     ax, ay, az = _areas(g)
-    fx = u * 0.5 * (np.roll(th, 1, axis=2) + th) * ax       # face i: cells i-1, i
-    fy = v * 0.5 * (np.roll(th, 1, axis=1) + th) * ay
+    px, py = g.x.periodic, g.y.periodic
+    if px and py:
+        fx = u * 0.5 * (np.roll(th, 1, axis=2) + th) * ax       # face i: cells i-1, i
+        fy = v * 0.5 * (np.roll(th, 1, axis=1) + th) * ay
+    else:
+        lx, hx_ = _sides(th, 2, px)
+        ly, hy_ = _sides(th, 1, py)
+        fx = _open(u * 0.5 * (lx + hx_) * ax, 2, px)
+        fy = _open(v * 0.5 * (ly + hy_) * ay, 1, py)
     nz = th.shape[0]
     fz = np.zeros((nz + 1,) + th.shape[1:])
     fz[1:nz] = w[1:nz] * 0.5 * (th[:-1] + th[1:]) * az[None]
-    net = (np.roll(fx, -1, axis=2) - fx) + (np.roll(fy, -1, axis=1) - fy) + (fz[1:] - fz[:-1])
+    net = _net(fx, 2, px) + _net(fy, 1, py) + (fz[1:] - fz[:-1])
     return -net / g.vol()
 
 
 def lap_h(g, th):
-    """Horizontal diffusion (1/V) sum over x and y faces of A_f (theta_R - theta_L)/dc_f."""
+    """Horizontal diffusion (1/V) sum over x and y faces of A_f (theta_R - theta_L)/dc_f;
+    no diffusive flux through a side wall (adiabatic)."""
     ax, ay, _ = _areas(g)
-    gx = (th - np.roll(th, 1, axis=2)) / g.x.dc[None, None, :] * ax
-    gy = (th - np.roll(th, 1, axis=1)) / g.y.dc[None, :, None] * ay
-    return ((np.roll(gx, -1, axis=2) - gx) + (np.roll(gy, -1, axis=1) - gy)) / g.vol()
+    px, py = g.x.periodic, g.y.periodic
+    if px and py:
+        gx = (th - np.roll(th, 1, axis=2)) / g.x.dc[None, None, :] * ax
+        gy = (th - np.roll(th, 1, axis=1)) / g.y.dc[None, :, None] * ay
+        return ((np.roll(gx, -1, axis=2) - gx) + (np.roll(gy, -1, axis=1) - gy)) / g.vol()
+    lx, hx_ = _sides(th, 2, px)
+    ly, hy_ = _sides(th, 1, py)
+    gx = _open((hx_ - lx) / g.x.dc[None, None, :] * ax, 2, px)
+    gy = _open((hy_ - ly) / g.y.dc[None, :, None] * ay, 1, py)
+    return (_net(gx, 2, px) + _net(gy, 1, py)) / g.vol()
 
 
 def z_matrix(g, tk, p):
@@ -187,30 +245,59 @@ def _lap_h_transpose(g, mu):
     """Lh^T mu, written as the transpose of the face-flux form of ``lap_h``."""
     ax, ay, _ = _areas(g)
     q = mu / g.vol()
-    tx = ax / g.x.dc[None, None, :] * (np.roll(q, 1, axis=2) - q)   # face i: d/d theta_i
-    ty = ay / g.y.dc[None, :, None] * (np.roll(q, 1, axis=1) - q)
-    return (tx - np.roll(tx, -1, axis=2)) + (ty - np.roll(ty, -1, axis=1))
+    px, py = g.x.periodic, g.y.periodic
+    if px and py:
+        tx = ax / g.x.dc[None, None, :] * (np.roll(q, 1, axis=2) - q)   # face i: d/d theta_i
+        ty = ay / g.y.dc[None, :, None] * (np.roll(q, 1, axis=1) - q)
+        return (tx - np.roll(tx, -1, axis=2)) + (ty - np.roll(ty, -1, axis=1))
+    # face f (cells lo, hi) carries F_f = w_f (theta_hi - theta_lo), added to lo's
+    # balance and subtracted from hi's; sum(q * Lh theta) = sum_f F_f (q_lo - q_hi),
+    # so with t_f = w_f (q_lo - q_hi) cell hi receives +t_f and cell lo -t_f
+    out = np.zeros_like(mu)
+    for axis, d, a, per in ((2, g.x.dc[None, None, :], ax, px), (1, g.y.dc[None, :, None], ay, py)):
+        lo, hi = _sides(q, axis, per)
+        t = _open(a / d * (lo - hi), axis, per)
+        out = out + _to_cells(-t, t, axis, per)
+    return out
 
 
 def _advection_transpose(g, mu, u, v, w):
-    """C_u^T mu: each face f (cells L, R) gives s_f = u_f A_f (q_R - q_L)/2 to both cells."""
+    """C_u^T mu: each face f (cells L, R) gives s_f = u_f A_f (q_R - q_L)/2 to both
+    cells; wall faces give nothing."""
     ax, ay, az = _areas(g)
     q = mu / g.vol()
-    sx = 0.5 * u * ax * (q - np.roll(q, 1, axis=2))
-    sy = 0.5 * v * ay * (q - np.roll(q, 1, axis=1))
     nz = mu.shape[0]
     sz = np.zeros((nz + 1,) + mu.shape[1:])
     sz[1:nz] = 0.5 * w[1:nz] * az[None] * (q[1:] - q[:-1])
-    return (sx + np.roll(sx, -1, axis=2)) + (sy + np.roll(sy, -1, axis=1)) + (sz[1:] + sz[:-1])
+    px, py = g.x.periodic, g.y.periodic
+    if px and py:
+        sx = 0.5 * u * ax * (q - np.roll(q, 1, axis=2))
+        sy = 0.5 * v * ay * (q - np.roll(q, 1, axis=1))
+        return (sx + np.roll(sx, -1, axis=2)) + (sy + np.roll(sy, -1, axis=1)) + (sz[1:] + sz[:-1])
+    out = sz[1:] + sz[:-1]
+    for axis, vel, a, per in ((2, u, ax, px), (1, v, ay, py)):
+        lo, hi = _sides(q, axis, per)
+        sf = _open(0.5 * vel * a * (hi - lo), axis, per)
+        out = out + _to_cells(sf, sf, axis, per)
+    return out
 
 
 def _advection_velocity_transpose(g, mu, th):
     """Gradient of sum(mu * C_u(theta)) w.r.t. every dense face velocity:
-    A_f (theta_L + theta_R)/2 (q_R - q_L); zero on the z walls."""
+    A_f (theta_L + theta_R)/2 (q_R - q_L); zero on every wall face."""
     ax, ay, az = _areas(g)
     q = mu / g.vol()
-    gu = ax * 0.5 * (np.roll(th, 1, axis=2) + th) * (q - np.roll(q, 1, axis=2))
-    gv = ay * 0.5 * (np.roll(th, 1, axis=1) + th) * (q - np.roll(q, 1, axis=1))
+    px, py = g.x.periodic, g.y.periodic
+    if px and py:
+        gu = ax * 0.5 * (np.roll(th, 1, axis=2) + th) * (q - np.roll(q, 1, axis=2))
+        gv = ay * 0.5 * (np.roll(th, 1, axis=1) + th) * (q - np.roll(q, 1, axis=1))
+    else:
+        tl, th_ = _sides(th, 2, px)
+        ql, qh = _sides(q, 2, px)
+        gu = _open(ax * 0.5 * (tl + th_) * (qh - ql), 2, px)
+        tl, th_ = _sides(th, 1, py)
+        ql, qh = _sides(q, 1, py)
+        gv = _open(ay * 0.5 * (tl + th_) * (qh - ql), 1, py)
     nz = th.shape[0]
     gw = np.zeros((nz + 1,) + th.shape[1:])
     gw[1:nz] = az[None] * 0.5 * (th[:-1] + th[1:]) * (q[1:] - q[:-1])
