@@ -64,13 +64,20 @@ typedef enum {
 
 typedef enum { MR_FP64 = 0, MR_FP32 = 1 } mr_precision;
 typedef enum { MR_DIRICHLET = 0, MR_ADIABATIC = 1 } mr_wall_bc;
+/* Side conditions in x and y: periodic, or adiabatic no-slip walls at both
+ * ends (the paper's cube, Sec. 4).  On a walled axis the face arrays keep
+ * their shape: face i of u still lies at xf[i], so u[..., 0] is the low wall
+ * and the high wall (xf[nx]) is not stored; the library treats both wall
+ * faces as zero velocity and zero diffusive flux, whatever the array holds at
+ * face 0, writes zero there, and reports zero gradient for it. */
+typedef enum { MR_PERIODIC = 0, MR_WALLS = 1 } mr_side;
 
 /* Problem description (host memory; copied by mr_init). */
 typedef struct {
   int32_t ncx, ncy, ncz;   /* coarse cells per axis (>= 3 where the refinement factor > 1) */
   int32_t mx, my, mz;      /* refinement factors M_x, M_y, M_z (>= 1), Sec. 3.1 */
-  const double* xf;        /* nx+1 dense x faces, strictly increasing; period xf[nx]-xf[0] */
-  const double* yf;        /* ny+1 dense y faces, strictly increasing; period yf[ny]-yf[0] */
+  const double* xf;        /* nx+1 dense x faces, strictly increasing; period xf[nx]-xf[0] (or walls) */
+  const double* yf;        /* ny+1 dense y faces, strictly increasing; period yf[ny]-yf[0] (or walls) */
   const double* zf;        /* nz+1 dense z faces, strictly increasing; walls at both ends */
   int32_t bc_bot, bc_top;  /* scalar condition on each wall (mr_wall_bc) */
   double t_bot, t_top;     /* wall values for MR_DIRICHLET */
@@ -78,6 +85,7 @@ typedef struct {
   double dt;               /* fixed time step (> 0) */
   int32_t n_avg;           /* averaging period N_p of Eq. 7 (0 = never) */
   int32_t precision;       /* mr_precision of every field buffer */
+  int32_t side_x, side_y;  /* mr_side of the x and y axes (0 = periodic) */
 } mr_desc;
 
 /* Nusselt summary of one scalar field (Eq. 22, instantaneous). */

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmrscalar
 MR_OK, MR_EINVAL, MR_ESHAPE, MR_EHIP, MR_ENOMEM, MR_ENONFINITE = 0, -1, -2, -3, -4, -5
 MR_FP64, MR_FP32 = 0, 1
 MR_DIRICHLET, MR_ADIABATIC = 0, 1
+MR_PERIODIC, MR_WALLS = 0, 1
 
 # every symbol the header declares
 EXPORTS = [
@@ -36,6 +37,7 @@ class mr_desc(ctypes.Structure):
         ("dt", c_double),
         ("n_avg", c_int32),
         ("precision", c_int32),
+        ("side_x", c_int32), ("side_y", c_int32),
     ]
 
 

@@ -17,12 +17,14 @@ from ._lib import MRError, check, lib, mr_desc, mr_nu
 
 _BC = {"dirichlet": _lib.MR_DIRICHLET, "adiabatic": _lib.MR_ADIABATIC}
 _PREC = {"fp64": _lib.MR_FP64, "fp32": _lib.MR_FP32}
+_SIDE = {"periodic": _lib.MR_PERIODIC, "walls": _lib.MR_WALLS}
 
 
 def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot="dirichlet",
-              bc_top="dirichlet", precision="fp64"):
+              bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic"):
     """Build an ``mr_desc``; returns (desc, keepalive) -- keep the second alive
-    while the descriptor is in use (it owns the face arrays)."""
+    while the descriptor is in use (it owns the face arrays).  side_x / side_y:
+    "periodic" or "walls" (adiabatic no-slip side walls)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
     mx, my, mz = (int(a) for a in m)
     n = [f.size - 1 for f in faces]
@@ -39,6 +41,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     d.ra, d.pr, d.dt = float(ra), float(pr), float(dt)
     d.n_avg = int(n_avg)
     d.precision = _PREC[precision]
+    d.side_x, d.side_y = _SIDE[side_x], _SIDE[side_y]
     return d, faces
 
 
@@ -74,10 +77,12 @@ class Context:
     """Grid tables on the current GPU plus typed entry points."""
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
-                 bc_bot="dirichlet", bc_top="dirichlet", precision="fp64"):
+                 bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
+                 side_y="periodic"):
         if not torch.cuda.is_available():
             raise RuntimeError("the multiple-resolution library needs a HIP GPU")
-        desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision)
+        desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision,
+                               side_x, side_y)
         self.desc, self._keep = desc, keep
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._ctx = c_void_p()

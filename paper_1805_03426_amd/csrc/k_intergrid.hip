@@ -76,17 +76,18 @@ template <typename T>
 __global__ void __launch_bounds__(256) diss_partial(const T* th, const double* hx, const double* hy,
                                                     const double* hz, const double* idxc,
                                                     const double* idyc, const double* dcz, int nx,
-                                                    int ny, int nz, int nbx, int kb, int dir_bot,
-                                                    int dir_top, double t_bot, double t_top,
-                                                    double* part) {
+                                                    int ny, int nz, int nbx, int kb, int walx, int waly,
+                                                    int dir_bot, int dir_top, double t_bot,
+                                                    double t_top, double* part) {
   __shared__ DD sh[3][256 / kWave];
   const int b = blockIdx.x;
   const int bx = b % nbx, j = (b / nbx) % ny, kc = b / (nbx * ny);
   const int i_raw = bx * 256 + threadIdx.x;
   const bool on = i_raw < nx;
   const int i = on ? i_raw : nx - 1;
-  const int im = i == 0 ? nx - 1 : i - 1;
-  const int jm = j == 0 ? ny - 1 : j - 1;
+  // across a side wall the neighbour is the cell itself: the wall face adds nothing
+  const int im = i == 0 ? (walx ? 0 : nx - 1) : i - 1;
+  const int jm = j == 0 ? (waly ? 0 : ny - 1) : j - 1;
   const size_t nxy = (size_t)nx * ny;
   const int k0 = kc * kb, k1 = min(nz, k0 + kb);
   const double wx = idxc[i] * hy[j], wy = idyc[j] * hx[i], area = hx[i] * hy[j];
@@ -195,11 +196,11 @@ hipError_t launch_dissipation(mr_ctx* c, const void* th, double* out, hipStream_
   if (c->precision == MR_FP64)
     hipLaunchKernelGGL(diss_partial<double>, dim3((unsigned)nb), dim3(256), 0, s, (const double*)th,
                        c->hx64, c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, nbx,
-                       kb, db, dtp, c->t_bot, c->t_top, c->red);
+                       kb, c->wx, c->wy, db, dtp, c->t_bot, c->t_top, c->red);
   else
     hipLaunchKernelGGL(diss_partial<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float*)th,
                        c->hx64, c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, nbx,
-                       kb, db, dtp, c->t_bot, c->t_top, c->red);
+                       kb, c->wx, c->wy, db, dtp, c->t_bot, c->t_top, c->red);
   hipLaunchKernelGGL(diss_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, (int)nb, c->vtot,
                      c->kappa * sqrt(c->ra * c->pr), out);
   return hipGetLastError();

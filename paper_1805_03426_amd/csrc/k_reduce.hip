@@ -23,7 +23,7 @@ constexpr int kDivBlocks = 2048;
 template <typename T>
 __global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const T* w, const double* hx,
                                                   const double* hy, const double* hz, int nx, int ny,
-                                                  int nz, double* part) {
+                                                  int nz, int wx, int wy, double* part) {
   __shared__ double sh[2][256 / kWave];
   const int nxy = nx * ny;
   const int64_t cells = (int64_t)nxy * nz;
@@ -35,8 +35,11 @@ __global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const 
     const int jp = j == ny - 1 ? 0 : j + 1;
     const int c0 = k * nxy + j * nx;
     const double ax = hy[j] * hz[k], ay = hx[i] * hz[k], az = hx[i] * hy[j];
-    const double ul = u[c0 + i], ur = u[c0 + ip];
-    const double vl = v[c0 + i], vr = v[k * nxy + jp * nx + i];
+    // side walls: the low wall face (stored) and the high one (not stored) carry nothing
+    const double ul = wx && i == 0 ? 0.0 : (double)u[c0 + i];
+    const double ur = wx && i == nx - 1 ? 0.0 : (double)u[c0 + ip];
+    const double vl = wy && j == 0 ? 0.0 : (double)v[c0 + i];
+    const double vr = wy && j == ny - 1 ? 0.0 : (double)v[k * nxy + jp * nx + i];
     const double wl = w[c0 + i], wr = w[c0 + nxy + i];
     const double dv = (ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az;
     const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
@@ -222,10 +225,12 @@ hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void
   if (e != hipSuccess) return e;
   if (c->precision == MR_FP64)
     hipLaunchKernelGGL(div_kernel<double>, dim3(nb), dim3(256), 0, s, (const double*)u, (const double*)v,
-                       (const double*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->red);
+                       (const double*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy,
+                       c->red);
   else
     hipLaunchKernelGGL(div_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)u, (const float*)v,
-                       (const float*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->red);
+                       (const float*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy,
+                       c->red);
   hipLaunchKernelGGL(max_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, nb, out);
   return hipGetLastError();
 }

@@ -8,7 +8,9 @@
 // the sub-cell under it.  The forward refinement runs the three stages in one
 // kernel with the intermediates in LDS (refine_fused); the three separate
 // stage kernels, with the intermediates in a context-owned buffer, serve the
-// shapes it does not cover (mz > 4 or a tile beyond its LDS budget).
+// cases it does not cover (side walls, mz > 4, a tile beyond its LDS budget).
+// Side walls: the low wall face of a walled axis is taken as zero velocity and
+// the high one (not stored) is zero, so the marches see no flow through walls.
 //
 // The transpose runs the stages in reverse order; a march becomes a suffix
 // sum inside each coarse cell, a split an R^T gather (no atomics: every output
@@ -38,6 +40,7 @@ struct RefArgs {
   T* out4;
   Geom<T> g;
   int nx, ny, nz, ncx, ncy, ncz, mx, my, mz;
+  int wx, wy;     // x / y bounded by walls: the wall faces carry zero velocity
 };
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -76,6 +79,11 @@ __global__ void __launch_bounds__(256) stage_z(RefArgs<T> A) {
     u1[r] = coarse_at(U, A.in3, s, kc * ncxy + J * ncx + Ip);
     v0[r] = coarse_at(V, A.in4, s, kc * ncxy + J * ncx + I);
     v1[r] = coarse_at(V, A.in4, s, kc * ncxy + Jp * ncx + I);
+    // side walls: the low wall face is taken as zero, the high one is not stored
+    if (A.wx && I == 0) u0[r] = T(0);
+    if (A.wx && I == ncx - 1) u1[r] = T(0);
+    if (A.wy && J == 0) v0[r] = T(0);
+    if (A.wy && J == ncy - 1) v1[r] = T(0);
   }
   const T iHX = A.g.iHX[I], iHY = A.g.iHY[J];
   T wv = coarse_at(W, A.in5, s, K * ncxy + J * ncx + I);
@@ -107,7 +115,7 @@ __global__ void __launch_bounds__(256) stage_y(RefArgs<T> A) {
   for (int r = 0; r < 3; ++r) {
     const int jc = A.g.sy[J * 3 + r];
     u0[r] = Uz[k * ncxy + jc * ncx + I];
-    u1[r] = Uz[k * ncxy + jc * ncx + Ip];
+    u1[r] = A.wx && I == ncx - 1 ? T(0) : Uz[k * ncxy + jc * ncx + Ip];
     w0[r] = Wz[k * ncxy + jc * ncx + I];
     w1[r] = Wz[(k + 1) * ncxy + jc * ncx + I];
   }
@@ -141,7 +149,7 @@ __global__ void __launch_bounds__(256) stage_x(RefArgs<T> A) {
   for (int r = 0; r < 3; ++r) {
     const int ic = A.g.sx[I * 3 + r];
     v0[r] = Vzy[k * nyx + j * ncx + ic];
-    v1[r] = Vzy[k * nyx + jp * ncx + ic];
+    v1[r] = A.wy && j == ny - 1 ? T(0) : Vzy[k * nyx + jp * ncx + ic];
     w0[r] = Wzy[k * nyx + j * ncx + ic];
     w1[r] = Wzy[(k + 1) * nyx + j * ncx + ic];
   }
@@ -464,7 +472,7 @@ __global__ void __launch_bounds__(256) tx_march(RefArgs<T> A) {
     tot += gu[k * nxy + j * nx + i];
     // adjoint of the march increment at sub-face p (zero for the last one)
     const T c0 = -suffix<T>(I, mx, p, [&](int q) { return gu[k * nxy + j * nx + q]; });
-    const T cjm = -suffix<T>(I, mx, p, [&](int q) { return gu[k * nxy + jm * nx + q]; });
+    const T cjm = A.wy && j == 0 ? T(0) : -suffix<T>(I, mx, p, [&](int q) { return gu[k * nxy + jm * nx + q]; });
     const T ckm = k > 0 ? -suffix<T>(I, mx, p, [&](int q) { return gu[(k - 1) * nxy + j * nx + q]; }) : T(0);
     A.out1[k * nxy + j * nx + i] = gv[k * nxy + j * nx + i] + cjm * hx * ihym - c0 * hx * ihy;
     A.out2[k * nxy + j * nx + i] = gw[k * nxy + j * nx + i] + ckm * hx * ihzm - c0 * hx * ihz;
@@ -485,10 +493,10 @@ __global__ void __launch_bounds__(256) tx_split(RefArgs<T> A) {
   const T* gv = A.in1;
   const T* gw = A.in2;
   A.out2[k * nyx + j * ncx + I] =
-      gather<T>(A.g.Rx, A.g.sx, ncx, mx, true, I, [&](int i) { return gw[k * nxy + j * nx + i]; });
+      gather<T>(A.g.Rx, A.g.sx, ncx, mx, !A.wx, I, [&](int i) { return gw[k * nxy + j * nx + i]; });
   if (k < nz)
     A.out1[k * nyx + j * ncx + I] =
-        gather<T>(A.g.Rx, A.g.sx, ncx, mx, true, I, [&](int i) { return gv[k * nxy + j * nx + i]; });
+        gather<T>(A.g.Rx, A.g.sx, ncx, mx, !A.wx, I, [&](int i) { return gv[k * nxy + j * nx + i]; });
 }
 
 // Y1: thread per (coarse I, coarse J, dense k).  in1 = gVzy; out0 = gUzy (+=),
@@ -510,7 +518,7 @@ __global__ void __launch_bounds__(256) ty_march(RefArgs<T> A) {
     const T hy = A.g.hy[j];
     tot += gV[k * nyx + j * ncx + I];
     const T c0 = -suffix<T>(J, my, p, [&](int q) { return gV[k * nyx + q * ncx + I]; });
-    const T cim = -suffix<T>(J, my, p, [&](int q) { return gV[k * nyx + q * ncx + Im]; });
+    const T cim = A.wx && I == 0 ? T(0) : -suffix<T>(J, my, p, [&](int q) { return gV[k * nyx + q * ncx + Im]; });
     const T ckm = k > 0 ? -suffix<T>(J, my, p, [&](int q) { return gV[(k - 1) * nyx + q * ncx + I]; }) : T(0);
     A.out0[k * nyx + j * ncx + I] += cim * hy * iHXm - c0 * hy * iHX;
     A.out2[k * nyx + j * ncx + I] += ckm * hy * ihzm - c0 * hy * ihz;
@@ -531,10 +539,10 @@ __global__ void __launch_bounds__(256) ty_split(RefArgs<T> A) {
   const T* gU = A.in0;
   const T* gW = A.in2;
   A.out2[k * ncxy + J * ncx + I] =
-      gather<T>(A.g.Ry, A.g.sy, ncy, my, true, J, [&](int j) { return gW[k * nyx + j * ncx + I]; });
+      gather<T>(A.g.Ry, A.g.sy, ncy, my, !A.wy, J, [&](int j) { return gW[k * nyx + j * ncx + I]; });
   if (k < nz)
     A.out0[k * ncxy + J * ncx + I] =
-        gather<T>(A.g.Ry, A.g.sy, ncy, my, true, J, [&](int j) { return gU[k * nyx + j * ncx + I]; });
+        gather<T>(A.g.Ry, A.g.sy, ncy, my, !A.wy, J, [&](int j) { return gU[k * nyx + j * ncx + I]; });
 }
 
 // Z1: thread per coarse cell (I, J, K).  in2 = gWz; out0 = gUz (+=),
@@ -555,8 +563,8 @@ __global__ void __launch_bounds__(256) tz_march(RefArgs<T> A) {
     const T hz = A.g.hz[k];
     tot += gWz[k * ncxy + J * ncx + I];
     const T c0 = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + J * ncx + I]; });
-    const T cim = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + J * ncx + Im]; });
-    const T cjm = -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + Jm * ncx + I]; });
+    const T cim = A.wx && I == 0 ? T(0) : -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + J * ncx + Im]; });
+    const T cjm = A.wy && J == 0 ? T(0) : -suffix<T>(K, mz, p, [&](int q) { return gWz[q * ncxy + Jm * ncx + I]; });
     A.out0[k * ncxy + J * ncx + I] += cim * hz * iHXm - c0 * hz * iHX;
     A.out1[k * ncxy + J * ncx + I] += cjm * hz * iHYm - c0 * hz * iHY;
   }
@@ -574,10 +582,13 @@ __global__ void __launch_bounds__(256) tz_split(RefArgs<T> A) {
   const int I = tid % ncx, J = (tid / ncx) % ncy, K = tid / ncxy;
   const T* gU = A.in0;
   const T* gV = A.in1;
+  // a low wall face is taken as zero by the forward map: its gradient is zero
   A.out0[K * ncxy + J * ncx + I] =
-      gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gU[k * ncxy + J * ncx + I]; });
+      A.wx && I == 0 ? T(0)
+                     : gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gU[k * ncxy + J * ncx + I]; });
   A.out1[K * ncxy + J * ncx + I] =
-      gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gV[k * ncxy + J * ncx + I]; });
+      A.wy && J == 0 ? T(0)
+                     : gather<T>(A.g.Rz, A.g.sz, ncz, mz, false, K, [&](int k) { return gV[k * ncxy + J * ncx + I]; });
 }
 
 // ---------------------------------------------------------------- launchers
@@ -591,6 +602,7 @@ RefArgs<T> ref_args(mr_ctx* c, const Geom<T>& g) {
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.ncx = c->ncx; a.ncy = c->ncy; a.ncz = c->ncz;
   a.mx = c->mx; a.my = c->my; a.mz = c->mz;
+  a.wx = c->wx; a.wy = c->wy;
   return a;
 }
 
@@ -628,7 +640,7 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
                     void* w, hipStream_t s) {
   const int TI = kFuseCols / c->mx;
   int TJ = 0;
-  if (TI >= 1 && c->mz <= kFuseMaxMz) {
+  if (TI >= 1 && c->mz <= kFuseMaxMz && !c->wx && !c->wy) {
     // rows per tile: every stage-z item (one per halo column and row) on its own lane
     TJ = std::min(std::min(MR_FUSED_ROWS, 256 / (TI + 3) - 2), c->ncy);
     while (TJ >= 1 && fused_lds<T>(TI, TJ, c->mx, c->my, c->mz) > kFuseMaxLds) --TJ;

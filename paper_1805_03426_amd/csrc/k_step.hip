@@ -39,6 +39,7 @@ struct LineArgs {
   T s2;                // BWD: 1 with lam_add, 0 without
   int nx, ny, nz, nch;
   int band;            // x tiles per band of the tile walk (see line_kernel)
+  int wx, wy;          // x / y bounded by adiabatic no-slip walls (else periodic)
 };
 
 // Values one z level of the stencil reads.
@@ -96,6 +97,10 @@ __device__ __forceinline__ double lane_shl(double v) {
 // the periodic continuation of the row (column i mod nx), so the lane after
 // the last column holds column 0, the periodic right neighbour of the last
 // column; such lanes never store.
+// Side walls: on a walled axis the neighbour across a wall is the cell itself
+// (lanes past the end repeat the last column), so no diffusive flux crosses
+// it, and the velocity on the wall faces is taken as zero, so no advective
+// flux crosses it either.
 //
 // Tile walk: the x tiles are grouped into bands of A.band tiles; a band is
 // walked row patch by row patch, x fastest inside the band.  Workgroups that
@@ -104,7 +109,7 @@ __device__ __forceinline__ double lane_shl(double v) {
 // the centre rows of another that reads them at nearly the same time (L2
 // hits), while the lines holding the x halo of a tile are shared with the
 // tiles beside it in the band.
-template <typename T, int L, int MODE, int ROWS, int MINB, int PFD>
+template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS>
 __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
@@ -123,14 +128,19 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   const int i_raw = xt * COLS + lane % COLS;
   const int j_raw = jt * ROWS + hrow;
   const bool act = i_raw < nx && j_raw < ny;
-  const int i = i_raw % nx;
-  // a row past the last one wraps around (periodic), so that the other half
-  // still sees the right neighbour row; its results are not stored
-  const int j = j_raw % ny;
-  const int im = i == 0 ? nx - 1 : i - 1;
-  const int ip = i == nx - 1 ? 0 : i + 1;
-  const int jm = j == 0 ? ny - 1 : j - 1;
-  const int jp = j == ny - 1 ? 0 : j + 1;
+  const bool wx = WALLS && A.wx, wy = WALLS && A.wy;
+  const int i = wx ? min(i_raw, nx - 1) : i_raw % nx;
+  // a row past the last one wraps around (periodic) or repeats the last row
+  // (walls), so that the other half still sees the right neighbour row; its
+  // results are not stored
+  const int j = wy ? min(j_raw, ny - 1) : j_raw % ny;
+  const int im = i == 0 ? (wx ? 0 : nx - 1) : i - 1;
+  const int ip = i == nx - 1 ? (wx ? nx - 1 : 0) : i + 1;
+  const int jm = j == 0 ? (wy ? 0 : ny - 1) : j - 1;
+  const int jp = j == ny - 1 ? (wy ? ny - 1 : 0) : j + 1;
+  // side faces that are walls (their velocity is taken as zero)
+  const bool zu0 = wx && i == 0, zu1 = wx && i == nx - 1;
+  const bool zv0 = wy && j == 0, zv1 = wy && j == ny - 1;
   const int nxy = nx * ny;
   const int k0 = c * L;
   // offsets of the stencil points inside one z level; a level's base pointer
@@ -238,6 +248,13 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
         cur.yp = hrow == ROWS - 1 ? fh : fup;
         cur.pym = hrow == 0 ? ph : pdn;
         cur.pyp = hrow == ROWS - 1 ? ph : pup;
+      }
+      if constexpr (WALLS) {
+        // wall faces carry no velocity (lane selects, branch-free)
+        cur.u0 = zu0 ? T(0) : cur.u0;
+        cur.u1 = zu1 ? T(0) : cur.u1;
+        cur.v0 = zv0 ? T(0) : cur.v0;
+        cur.v1 = zv1 ? T(0) : cur.v1;
       }
       const T zp = cur.zp, w1 = cur.w1;
       const T ihz = g.ihz[kc];
@@ -365,9 +382,12 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   const dim3 grid((unsigned)(ntx * nty));
   const dim3 block(kWave, c->nch);
   switch (c->L) {
-#define MR_CASE(LL)                                                             \
-  case LL:                                                                      \
-    hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf>), grid, block, 0, s, a); \
+#define MR_CASE(LL)                                                                        \
+  case LL:                                                                                 \
+    if (a.wx || a.wy)                                                                      \
+      hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf, true>), grid, block, 0, s, a);  \
+    else                                                                                   \
+      hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf, false>), grid, block, 0, s, a); \
     break;
     MR_CASE(8)
     MR_CASE(16)
@@ -390,6 +410,8 @@ LineArgs<T> base_args(mr_ctx* c, const Geom<T>& g) {
   a.ny = c->ny;
   a.nz = c->nz;
   a.nch = c->nch;
+  a.wx = c->wx;
+  a.wy = c->wy;
   return a;
 }
 
@@ -463,11 +485,13 @@ struct GradArgs {
   T* gw;
   Geom<T> g;
   int nx, ny, nz;
+  int wx, wy;
 };
 
 // One thread per dense cell (i, j, k) owns the faces on its low side: x-face i,
 // y-face j and, for k >= 1, z-face k.  The walls' z faces carry no advective
-// flux, so their gradient stays as it is.
+// flux, so their gradient stays as it is; a side-wall face (x-face 0 or
+// y-face 0 of a walled axis) gets zero.
 template <typename T>
 __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
   const int nx = A.nx, ny = A.ny, nz = A.nz;
@@ -497,6 +521,8 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
       sw += A.tau[s] * gz;
     }
   }
+  if (A.wx && i == 0) su = T(0);
+  if (A.wy && j == 0) sv = T(0);
   A.gu[row + i] += su;
   A.gv[row + i] += sv;
   if (k > 0) A.gw[row + i] += sw;
@@ -521,6 +547,8 @@ hipError_t grad_t(mr_ctx* c, const Geom<T>& g, int count, const int64_t* steps,
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
+  a.wx = c->wx;
+  a.wy = c->wy;
   const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
   hipLaunchKernelGGL(grad_kernel<T>, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();

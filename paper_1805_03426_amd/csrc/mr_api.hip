@@ -165,9 +165,11 @@ int check_desc(const mr_desc* d, Problem& P) {
   if (!(d->ra > 0.0) || !(d->pr > 0.0) || !std::isfinite(d->ra * d->pr)) return MR_EINVAL;
   if (d->n_avg < 0) return MR_EINVAL;
   if (!std::isfinite(d->t_bot) || !std::isfinite(d->t_top)) return MR_EINVAL;
+  if ((d->side_x != MR_PERIODIC && d->side_x != MR_WALLS) || (d->side_y != MR_PERIODIC && d->side_y != MR_WALLS))
+    return MR_EINVAL;
   int st;
-  if ((st = build_axis(d->xf, (int)nx, d->mx, true, P.x)) != MR_OK) return st;
-  if ((st = build_axis(d->yf, (int)ny, d->my, true, P.y)) != MR_OK) return st;
+  if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
+  if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
   if ((st = build_axis(d->zf, (int)nz, d->mz, false, P.z)) != MR_OK) return st;
   P.kappa = 1.0 / sqrt(d->ra * d->pr);
   // explicit x/y diffusion: the leapfrog step is forward Euler over 2 dt
@@ -484,6 +486,8 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   c->kappa = P.kappa; c->dt = desc->dt; c->ra = desc->ra; c->pr = desc->pr;
   c->t_bot = desc->t_bot; c->t_top = desc->t_top;
   c->bc_bot = desc->bc_bot; c->bc_top = desc->bc_top; c->n_avg = desc->n_avg;
+  c->wx = desc->side_x == MR_WALLS;
+  c->wy = desc->side_y == MR_WALLS;
   c->L = L; c->nch = nch;
   for (int k = 0; k < mr::NKINDS; ++k) c->tau[k] = taus[k];
   {

@@ -64,6 +64,7 @@ struct mr_ctx {
   int precision;
   double kappa, dt, ra, pr, t_bot, t_top;
   int bc_bot, bc_top, n_avg;
+  int wx, wy;                      // x / y bounded by adiabatic no-slip walls (else periodic)
   int device;
   int last_err;
   int L, nch;                      // z chunk length and count of the line solver

@@ -52,6 +52,22 @@ def test_host_refinement_tables_match_oracle(m):
                 assert s[I] == O.stencil_start(ax, I)
 
 
+@pytest.mark.parametrize("m", [(2, 3, 2), (3, 2, 2)])
+def test_host_refinement_tables_with_side_walls(m):
+    """Walled x and y: one-sided stencils at the first and last coarse cells."""
+    nc = (5, 4, 4)
+    xf, yf, zf = (inputs.uniform_faces(c * q) for c, q in zip(nc, m))
+    zf = inputs.tanh_faces(nc[2] * m[2], 1.5)
+    d, keep = make_desc(xf, yf, zf, m, ra=1e4, pr=1.0, dt=1e-5, side_x="walls", side_y="walls")
+    g = O.Grid(xf, yf, zf, m, periodic=(False, False, False))
+    for axis, ax in enumerate((g.x, g.y)):
+        R, s = host_refinement_table(d, axis)
+        for I in range(ax.nc):
+            np.testing.assert_allclose(R[I], O.r_matrix(ax, I), rtol=0, atol=1e-14)
+            assert s[I] == O.stencil_start(ax, I)
+    assert host_refinement_table(d, 0)[1][0] == 0 and host_refinement_table(d, 0)[1][-1] == nc[0] - 3
+
+
 def test_host_refinement_stretched_x():
     rng = np.random.default_rng(3)
     hx = rng.uniform(0.5, 2.0, 12)
@@ -95,7 +111,7 @@ def _init_status(**over):
 
 @pytest.mark.parametrize("field,value", [
     ("mx", 0), ("ncz", 0), ("ncx", 2), ("dt", 0.0), ("dt", -1.0), ("ra", 0.0), ("pr", -2.0),
-    ("bc_bot", 7), ("precision", 5), ("n_avg", -1), ("dt", float("nan")),
+    ("bc_bot", 7), ("precision", 5), ("n_avg", -1), ("dt", float("nan")), ("side_x", 2), ("side_y", -1),
 ])
 def test_init_rejects_bad_descriptor(field, value):
     assert _init_status(**{field: value}) == _lib.MR_EINVAL
