@@ -9,7 +9,8 @@ value = dense-cell updates per second over the whole job.
 Also reported, outside the timed region: the same workload with FP32 storage,
 the adjoint workload (FP32, 20 steps, checkpoint every 5: forward and backward
 times), the inter-grid kernels (integration, Nu_T, refinement in time, one
-coarse step of M_t = 4), the FP32 step kernel on the 576^3 and
+coarse step of M_t = 4), the step and refinement with side walls in x and y,
+the FP32 step kernel on the 576^3 and
 1024x1024x512 workloads, the copy-kernel bandwidth, the roofline of the
 dominant kernel (the fused scalar step) and the oracle's CPU time on a
 bounded sample.
@@ -43,10 +44,12 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "scalar_step_rb256_fp64_traffic
 
 
 def kernel_source_hash():
-    """Hash of the HIP sources, to tell whether committed counters are stale."""
+    """Hash of the sources that define the scalar-step kernel (its code, the
+    shared header and the host tables and chunk choice), to tell whether the
+    committed counters of that kernel are stale."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1805_03426_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for name in ("k_step.hip", "mr_internal.h", "mr_api.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1805_03426_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -262,6 +265,34 @@ def large_fp32_step_times():
     return out
 
 
+def walls_times(w):
+    """The workload's FP64 step and refinement with adiabatic no-slip side
+    walls in x and y (the generator's coarse velocity with its low wall faces
+    zeroed): mean kernel times and % of HBM peak."""
+    from paper_1805_03426_amd.context import Context
+    d = inputs.workload_inputs(w)
+    ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, side_x="walls",
+                  side_y="walls")
+    U, V, W = (torch.from_numpy(d[k]).to("cuda", torch.float64) for k in ("U", "V", "W"))
+    U[:, :, 0] = 0.0
+    V[:, 0, :] = 0.0
+    u, v, w_ = ctx.empty(ctx.shape_cell), ctx.empty(ctx.shape_cell), ctx.empty(ctx.shape_w)
+    ref_ms = _event_ms(lambda: ctx.interpolate_velocity(U, V, W, out=(u, v, w_)), reps=10)
+    ring = [torch.from_numpy(d["theta0"]).to("cuda", torch.float64)] + [ctx.empty(ctx.shape_cell) for _ in range(3)]
+    runner = ctx.step_runner(ring, u, v, w_)
+    state = {"n": 0, "prev": 0, "cur": 0}
+
+    def step():
+        n, out = state["n"], 1 + state["n"] % 3
+        runner.step(n, state["prev"], state["cur"], out)
+        state.update(n=n + 1, prev=state["cur"], cur=out)
+
+    ms = _event_ms(step, reps=20, warmup=3)
+    ctx.close()
+    return dict(step_kernel_ms=ms, step_hbm_frac_alg=48 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                refine_ms=ref_ms)
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle's FP64 scalar step on the same workload, a bounded sample:
     as many whole-field steps as fit in the budget (at least one)."""
@@ -336,6 +367,9 @@ def main():
         torch.cuda.empty_cache()
         print("bench: inter-grid kernels", file=sys.stderr, flush=True)
         extras["intergrid"] = intergrid_times(w)
+        torch.cuda.empty_cache()
+        print("bench: side walls", file=sys.stderr, flush=True)
+        extras["walls_xy"] = walls_times(w)
         torch.cuda.empty_cache()
         print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
         extras["fp32_large"] = large_fp32_step_times()
