@@ -13,6 +13,10 @@ Readings (each also listed in the design notes):
 * the first step (n = 0) is forward Euler over dt with the same implicit z
   part; the averaging step produces theta^{n+1} when (n+1) mod N_p = 0, n >= 1,
   with its diffusion on level n-1 as written in Eq. 7;
+* optionally only a fraction 1 - w of the z diffusion is implicit, the rest
+  explicit on the lagged level (the level of the x/y diffusion): w = 1/2 is the
+  Crank-Nicolson weighting across the step's time span, w = 0 (default) fully
+  implicit;
 * z walls: Dirichlet (wall value at half a cell from the first centre) or
   adiabatic; x and y periodic, or bounded by adiabatic no-slip side walls (the
   paper's cube, Sec. 4): a wall face carries neither advective nor diffusive
@@ -45,6 +49,7 @@ class ScalarParams:
     bc_top: str = DIRICHLET
     ra: float = 1.0              # Ra and Pr enter Nu through (Ra Pr)^(1/2)
     pr: float = 1.0
+    z_explicit: float = 0.0      # w: share of the z diffusion taken explicit on the lagged level
 
     @staticmethod
     def from_ra_pr(ra, pr, dt, **kw):
@@ -172,6 +177,25 @@ def z_matrix(g, tk, p):
     return sub, diag, sup, bz
 
 
+def lz0(g, p, th):
+    """Lz0 theta: the vertical diffusion per unit volume without the wall
+    source (row k: the coefficients of I - Lz0 from ``z_matrix`` with tk = 1)."""
+    sub, diag, sup, _ = z_matrix(g, 1.0, p)
+    out = (1.0 - diag)[:, None, None] * th
+    out[1:] -= sub[1:, None, None] * th[:-1]
+    out[:-1] -= sup[:-1, None, None] * th[1:]
+    return out
+
+
+def lz0_transpose(g, p, mu):
+    """Lz0^T mu (the z system is not symmetric on a stretched grid)."""
+    sub, diag, sup, _ = z_matrix(g, 1.0, p)
+    out = (1.0 - diag)[:, None, None] * mu
+    out[:-1] -= sub[1:, None, None] * mu[1:]      # row k+1 couples column k through sub_{k+1}
+    out[1:] -= sup[:-1, None, None] * mu[:-1]     # row k-1 couples column k through sup_{k-1}
+    return out
+
+
 def thomas(sub, diag, sup, r):
     """Solve the tridiagonal system along axis 0 of r (classical Thomas algorithm)."""
     n = diag.size
@@ -193,15 +217,19 @@ def thomas(sub, diag, sup, r):
 def scalar_step(g, p, n, th_prev, th_cur, u, v, w):
     """theta^{n+1} from theta^{n-1}, theta^n (Eqs. 6-7 with implicit z diffusion):
 
-    (I - tau kappa Lz0) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
-                                      + tau [C(theta^n) + kappa Lh(theta^lag) + kappa bz]
-    with theta^lag = theta^{n-1} (theta^0 at n = 0); th_prev is ignored at n = 0."""
+    (I - (1-w) tau kappa Lz0) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
+        + tau [C(theta^n) + kappa Lh(theta^lag) + w kappa Lz0(theta^lag) + kappa bz]
+    with theta^lag = theta^{n-1} (theta^0 at n = 0), w = p.z_explicit;
+    th_prev is ignored at n = 0."""
     tau, ap, ac, _ = step_kind(n, p.n_avg, p.dt)
     lag = th_cur if n == 0 else th_prev
     r = ac * th_cur + tau * (advection(g, th_cur, u, v, w) + p.kappa * lap_h(g, lag))
     if n > 0:
         r = r + ap * th_prev
-    sub, diag, sup, bz = z_matrix(g, tau * p.kappa, p)
+    wz = p.z_explicit
+    if wz:
+        r = r + (tau * p.kappa * wz) * lz0(g, p, lag)
+    sub, diag, sup, bz = z_matrix(g, tau * p.kappa * (1.0 - wz), p)
     r = r + (tau * p.kappa) * bz[:, None, None]
     return thomas(sub, diag, sup, r)
 
@@ -308,20 +336,23 @@ def step_vjp(g, p, n, th_cur, u, v, w, lam_next):
     """Vector-Jacobian product of ``scalar_step`` at step n.
 
     Given lam_next = dL/dtheta^{n+1}, returns (g_prev, g_cur, gu, gv, gw) with
-    mu = (I - tau kappa Lz0)^-T lam_next,
-    g_prev = a_p mu + tau kappa Lh^T mu          (n >= 1; zero at n = 0)
-    g_cur  = a_c mu + tau C_u^T mu (+ tau kappa Lh^T mu at n = 0)
+    mu = (I - (1-w) tau kappa Lz0)^-T lam_next,
+    g_prev = a_p mu + tau kappa (Lh^T + w Lz0^T) mu      (n >= 1; zero at n = 0)
+    g_cur  = a_c mu + tau C_u^T mu (+ tau kappa (Lh^T + w Lz0^T) mu at n = 0)
     g_vel  = tau dC/du^T mu on every dense face.
     The tridiagonal transpose is formed explicitly (the matrix is not symmetric
     on a stretched grid)."""
     tau, ap, ac, _ = step_kind(n, p.n_avg, p.dt)
-    sub, diag, sup, _ = z_matrix(g, tau * p.kappa, p)
+    wz = p.z_explicit
+    sub, diag, sup, _ = z_matrix(g, tau * p.kappa * (1.0 - wz), p)
     sub_t = np.zeros_like(sub)
     sup_t = np.zeros_like(sup)
     sub_t[1:] = sup[:-1]
     sup_t[:-1] = sub[1:]
     mu = thomas(sub_t, diag, sup_t, lam_next)
     lh = (tau * p.kappa) * _lap_h_transpose(g, mu)
+    if wz:
+        lh = lh + (tau * p.kappa * wz) * lz0_transpose(g, p, mu)
     g_cur = ac * mu + tau * _advection_transpose(g, mu, u, v, w)
     if n == 0:
         g_cur = g_cur + lh
