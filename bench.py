@@ -293,6 +293,30 @@ def walls_times(w):
                 refine_ms=ref_ms)
 
 
+def zweight_times(w, z_explicit=0.5):
+    """The workload's FP64 step with a share w of the z diffusion explicit on
+    the lagged level (w = 1/2, Crank-Nicolson across the step span): mean
+    kernel time and % of HBM peak (the same algorithmic 48 B per cell)."""
+    from paper_1805_03426_amd.context import Context
+    d = inputs.workload_inputs(w)
+    ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, z_explicit=z_explicit)
+    U, V, W = (torch.from_numpy(d[k]).to("cuda", torch.float64) for k in ("U", "V", "W"))
+    u, v, w_ = ctx.interpolate_velocity(U, V, W)
+    ring = [torch.from_numpy(d["theta0"]).to("cuda", torch.float64)] + [ctx.empty(ctx.shape_cell) for _ in range(3)]
+    runner = ctx.step_runner(ring, u, v, w_)
+    state = {"n": 0, "prev": 0, "cur": 0}
+
+    def step():
+        n, out = state["n"], 1 + state["n"] % 3
+        runner.step(n, state["prev"], state["cur"], out)
+        state.update(n=n + 1, prev=state["cur"], cur=out)
+
+    ms = _event_ms(step, reps=20, warmup=3)
+    ctx.close()
+    return dict(z_explicit=z_explicit, step_kernel_ms=ms,
+                step_hbm_frac_alg=48 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle's FP64 scalar step on the same workload, a bounded sample:
     as many whole-field steps as fit in the budget (at least one)."""
@@ -370,6 +394,9 @@ def main():
         torch.cuda.empty_cache()
         print("bench: side walls", file=sys.stderr, flush=True)
         extras["walls_xy"] = walls_times(w)
+        torch.cuda.empty_cache()
+        print("bench: step with an explicit z share", file=sys.stderr, flush=True)
+        extras["z_explicit"] = zweight_times(w)
         torch.cuda.empty_cache()
         print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
         extras["fp32_large"] = large_fp32_step_times()

@@ -86,6 +86,9 @@ typedef struct {
   int32_t n_avg;           /* averaging period N_p of Eq. 7 (0 = never) */
   int32_t precision;       /* mr_precision of every field buffer */
   int32_t side_x, side_y;  /* mr_side of the x and y axes (0 = periodic) */
+  double z_explicit;       /* w in [0, 1/2]: share of the z diffusion taken explicit on the
+                              lagged level (0 = fully implicit, 1/2 = Crank-Nicolson across
+                              the step's time span; a reading of Sec. 2.2's implicit z) */
 } mr_desc;
 
 /* Nusselt summary of one scalar field (Eq. 22, instantaneous). */
@@ -140,10 +143,11 @@ int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w,
 /* ------------------------------------------------------------ scalar step */
 
 /* theta^{n+1} from theta^{n-1} and theta^n (Eqs. 6-7, z diffusion implicit):
- *   (I - tau kappa Lz) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
- *        + tau [C_u(theta^n) + kappa Lh(theta^lag) + kappa b_z]
+ *   (I - (1-w) tau kappa Lz0) theta^{n+1} = a_p theta^{n-1} + a_c theta^n
+ *        + tau [C_u(theta^n) + kappa Lh(theta^lag) + w kappa Lz0(theta^lag) + kappa b_z]
  * with C_u the central-flux advection (face value = mean of the two cells, no
- * flux through the walls), Lh the x/y diffusion, b_z the Dirichlet wall source,
+ * flux through the walls), Lh the x/y diffusion, Lz0 the z diffusion without
+ * the wall values, b_z the Dirichlet wall source, w = desc->z_explicit,
  * and per step type
  *   n = 0 (start-up):          tau = dt,     a_p = 0,   a_c = 1,   lag = n
  *   (n+1) mod N_p = 0, n >= 1: tau = 1.5 dt, a_p = 1/2, a_c = 1/2, lag = n-1
@@ -259,8 +263,9 @@ int mr_copy_probe(const void* src, void* dst, int64_t nbytes, void* stream);
  * may be -1 on a periodic axis).  Either pointer may be NULL. */
 int mr_host_refinement_table(const mr_desc* desc, int32_t axis, double* R_out, int32_t* start_out);
 
-/* Host-only: the tridiagonal (sub, diag, sup) of I - tau_n kappa Lz and the wall
- * source b_z (each nz doubles, any may be NULL) used by step n, and *tau_out. */
+/* Host-only: the tridiagonal (sub, diag, sup) of I - (1-w) tau_n kappa Lz0 and
+ * the wall source b_z (each nz doubles, any may be NULL) used by step n, and
+ * *tau_out (w = desc->z_explicit). */
 int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, double* sup,
                      double* bz, double* tau_out);
 

@@ -38,6 +38,7 @@ class mr_desc(ctypes.Structure):
         ("n_avg", c_int32),
         ("precision", c_int32),
         ("side_x", c_int32), ("side_y", c_int32),
+        ("z_explicit", c_double),
     ]
 
 

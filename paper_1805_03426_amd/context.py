@@ -21,10 +21,12 @@ _SIDE = {"periodic": _lib.MR_PERIODIC, "walls": _lib.MR_WALLS}
 
 
 def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot="dirichlet",
-              bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic"):
+              bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic",
+              z_explicit=0.0):
     """Build an ``mr_desc``; returns (desc, keepalive) -- keep the second alive
     while the descriptor is in use (it owns the face arrays).  side_x / side_y:
-    "periodic" or "walls" (adiabatic no-slip side walls)."""
+    "periodic" or "walls" (adiabatic no-slip side walls); z_explicit: share w of
+    the z diffusion taken explicit on the lagged level (0 to 1/2)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
     mx, my, mz = (int(a) for a in m)
     n = [f.size - 1 for f in faces]
@@ -42,6 +44,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     d.n_avg = int(n_avg)
     d.precision = _PREC[precision]
     d.side_x, d.side_y = _SIDE[side_x], _SIDE[side_y]
+    d.z_explicit = float(z_explicit)
     return d, faces
 
 
@@ -78,11 +81,11 @@ class Context:
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
                  bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
-                 side_y="periodic"):
+                 side_y="periodic", z_explicit=0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("the multiple-resolution library needs a HIP GPU")
         desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision,
-                               side_x, side_y)
+                               side_x, side_y, z_explicit)
         self.desc, self._keep = desc, keep
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._ctx = c_void_p()

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kIntBlock) integrate_kernel(const T* th, T* tc
 // lines) and the row j-1 value, and accumulates the faces on the low side of
 // its cell (plus the top plate for the last level).  Fixed partition:
 // part[b] holds workgroup b's three double-double sums.
-constexpr int kDissMaxParts = 8192;
+constexpr int kDissMaxParts = 2048;
 
 template <typename T>
 __global__ void __launch_bounds__(256) diss_partial(const T* th, const double* hx, const double* hy,
@@ -138,12 +138,16 @@ __global__ void __launch_bounds__(256) diss_partial(const T* th, const double* h
   }
 }
 
-// One wavefront: strided double-double merge of the partials, then the
-// shuffle tree; out = {Nu_T, <theta_x^2>, <theta_y^2>, <theta_z^2>}.
-__global__ void __launch_bounds__(kWave) diss_final(const double* part, int nb, double vtot,
-                                                    double nufac, double* out) {
+// One workgroup: strided double-double merge of the partials, the shuffle
+// tree in each wavefront, then the four wavefronts in order;
+// out = {Nu_T, <theta_x^2>, <theta_y^2>, <theta_z^2>}.
+constexpr int kDissFinal = 256;
+
+__global__ void __launch_bounds__(kDissFinal) diss_final(const double* part, int nb, double vtot,
+                                                         double nufac, double* out) {
+  __shared__ DD sh[3][kDissFinal / kWave];
   DD sx{0.0, 0.0}, sy{0.0, 0.0}, sz{0.0, 0.0};
-  for (int p = threadIdx.x; p < nb; p += kWave) {
+  for (int p = threadIdx.x; p < nb; p += kDissFinal) {
     const double* o = part + (size_t)p * 6;
     sx = dd_merge(sx, DD{o[0], o[1]});
     sy = dd_merge(sy, DD{o[2], o[3]});
@@ -152,7 +156,19 @@ __global__ void __launch_bounds__(kWave) diss_final(const double* part, int nb, 
   sx = wave_sum(sx);
   sy = wave_sum(sy);
   sz = wave_sum(sz);
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sh[0][wv] = sx;
+    sh[1][wv] = sy;
+    sh[2][wv] = sz;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int q = 1; q < kDissFinal / kWave; ++q) {
+      sx = dd_merge(sx, sh[0][q]);
+      sy = dd_merge(sy, sh[1][q]);
+      sz = dd_merge(sz, sh[2][q]);
+    }
     const double gx = (sx.s + sx.c) / vtot, gy = (sy.s + sy.c) / vtot, gz = (sz.s + sz.c) / vtot;
     out[0] = nufac * (gx + gy + gz);
     out[1] = gx;
@@ -201,7 +217,7 @@ hipError_t launch_dissipation(mr_ctx* c, const void* th, double* out, hipStream_
     hipLaunchKernelGGL(diss_partial<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float*)th,
                        c->hx64, c->areaw, c->hz64, g.idxc, g.idyc, c->dcz, c->nx, c->ny, c->nz, nbx,
                        kb, c->wx, c->wy, db, dtp, c->t_bot, c->t_top, c->red);
-  hipLaunchKernelGGL(diss_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, (int)nb, c->vtot,
+  hipLaunchKernelGGL(diss_final, dim3(1), dim3(kDissFinal), 0, s, (const double*)c->red, (int)nb, c->vtot,
                      c->kappa * sqrt(c->ra * c->pr), out);
   return hipGetLastError();
 }

@@ -14,6 +14,12 @@
 // x = x_hat + D G + X B (G, B precomputed because the matrix is the same for
 // every line).  Each cell is read once and written once: no intermediate
 // field goes back to HBM.
+//
+// Optionally a share w of the z diffusion is explicit on the lagged level
+// (w = 1/2: Crank-Nicolson across the step's time span): the solved system is
+// I - (1-w) tau kappa Lz0, and the right-hand side gains w tau kappa Lz0
+// applied to the lagged level (the reverse step: its transpose applied to the
+// adjoint of the step that reads the level as its lag).
 #include <string.h>
 
 #include "mr_internal.h"
@@ -36,6 +42,7 @@ struct LineArgs {
   ZSys z;        // system solved for the output (FWD: step n; BWD: transpose of step n-1)
   T ap, ac, tau, tk;   // FWD: step n;  BWD: a_c(n), tau_n, tau_n kappa (ap unused)
   T ap1, tk1;          // BWD: a_p(n+1), tau_{n+1} kappa (0 when there is no step n+1)
+  T tkw, tkw1;         // w tk and w tk1: explicit share of the z diffusion (EXPZ kernels)
   T s2;                // BWD: 1 with lam_add, 0 without
   int nx, ny, nz, nch;
   int band;            // x tiles per band of the tile walk (see line_kernel)
@@ -49,6 +56,7 @@ struct Lvl {
   T xm, xp, ym, yp;         // x/y neighbours of the z-stencil field
   T u0, u1, v0, v1;         // u on faces i, i+1; v on faces j, j+1
   T pc, pxm, pxp, pym, pyp; // second field (theta^{n-1} or mu^{n+1}) and its x/y neighbours
+  T pzp;                    // second field one level up (EXPZ only)
   T q;                      // lam_add (reverse step)
 };
 
@@ -109,8 +117,14 @@ __device__ __forceinline__ double lane_shl(double v) {
 // the centre rows of another that reads them at nearly the same time (L2
 // hits), while the lines holding the x halo of a tile are shared with the
 // tiles beside it in the band.
-template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS>
+//
+// EXPZ: the second field (the lagged level, or the adjoint of the step that
+// reads this level as its lag) also needs its z neighbours: the level above is
+// one more load per level, which is the next level's centre value (reused
+// there instead of loaded again), and the level below is carried.
+template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS, bool EXPZ>
 __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
+  static_assert(!(EXPZ && MODE == SEED), "the seed solve has no explicit part");
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
   const int lane = threadIdx.x;
@@ -171,16 +185,19 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   // second stencil field: theta^{n-1} (FWD) or mu^{n+1} (BWD, a0 with zero weights if absent)
   const T* p = MODE == FWD ? A.a0 : A.a1;
   T zm = T(0), zc = T(0), w0 = T(0);
+  T pzm = T(0), pnext = T(0);
   if (MODE != SEED) {
     zc = ldb(f + k0 * nxy, oc);
     zm = ldb(f + max(k0 - 1, 0) * nxy, oc);
     w0 = ldb(A.w + k0 * nxy, oc);
+    if constexpr (EXPZ) pzm = ldb(p + max(k0 - 1, 0) * nxy, oc);
   }
 
-  // All loads of one z level.  Rows k >= nz (padding of the last chunk) read
+  // All loads of level k0 + kk.  Rows k >= nz (padding of the last chunk) read
   // the top level; their values never reach a real row (decoupled identity rows).
-  auto fetch = [&](int k) {
+  auto fetch = [&](int kk) {
     Lvl<T> v;
+    const int k = k0 + kk;
     const int kc = min(k, nz - 1);
     if (MODE == SEED) {
       v.pc = ldb(A.a0 + kc * nxy, oc);
@@ -203,7 +220,14 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
     }
     v.u0 = ldb(uk, oc);
     v.v0 = ldb(vk, oc); v.v1 = ldb(vk, oyp);
-    v.pc = ldb(pk, oc);
+    if constexpr (EXPZ) {
+      // levels are fetched in order, so pnext holds this level's centre value
+      v.pc = kk > 0 ? pnext : ldb(pk, oc);
+      v.pzp = ldb(p + min(k + 1, nz - 1) * nxy, oc);
+      pnext = v.pzp;
+    } else {
+      v.pc = ldb(pk, oc);
+    }
     if constexpr (ROWS == 1) {
       v.ym = ldb(fk, oym); v.yp = ldb(fk, oyp);
       v.pym = ldb(pk, oym); v.pyp = ldb(pk, oyp);
@@ -216,15 +240,15 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   };
 
   // PFD levels ahead of the one being computed have their loads in flight
-  Lvl<T> cur = fetch(k0);
+  Lvl<T> cur = fetch(0);
   Lvl<T> n1, n2;
-  if (PFD >= 2 && L > 1) n1 = fetch(k0 + 1);
+  if (PFD >= 2 && L > 1) n1 = fetch(1);
 #pragma unroll
   for (int kk = 0; kk < L; ++kk) {
     const int k = k0 + kk;
     const int kc = min(k, nz - 1);
-    if (PFD == 1 && kk + 1 < L) n1 = fetch(k + 1);
-    if (PFD == 2 && kk + 2 < L) n2 = fetch(k + 2);
+    if (PFD == 1 && kk + 1 < L) n1 = fetch(kk + 1);
+    if (PFD == 2 && kk + 2 < L) n2 = fetch(kk + 2);
     T r;
     if (MODE == SEED) {
       r = cur.pc;
@@ -269,6 +293,8 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
         const T lap = ((cur.pxp - cur.pc) * idx1 - (cur.pc - cur.pxm) * idx0) * ihx +
                       ((cur.pyp - cur.pc) * idy1 - (cur.pc - cur.pym) * idy0) * ihy;
         r = A.ap * cur.pc + A.ac * zc + A.tau * adv + A.tk * lap;
+        if constexpr (EXPZ)   // explicit share of the z diffusion of the lagged level
+          r += A.tkw * (g.lzd[k] * cur.pc + g.lzl[k] * pzm + g.lzh[k] * cur.pzp);
       } else {
         // C_u^T mu^n: each face f (cells L, R) adds u_f (mu_R/h_R - mu_L/h_L)/2 to both cells
         const T qc_x = zc * ihx, qc_y = zc * ihy, qc_z = zc * ihz;
@@ -286,11 +312,15 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
           const T l0 = ((cur.xm * ihxm - qc_x) * idx0 - (qc_x - cur.xp * ihxp) * idx1) +
                        ((cur.ym * ihym - qc_y) * idy0 - (qc_y - cur.yp * ihyp) * idy1);
           r += A.tk * l0;
+          if constexpr (EXPZ) r += A.tkw * (g.lzd[k] * zc + g.lztl[k] * zm + g.lzth[k] * zp);
         }
+        if constexpr (EXPZ)   // step n+1's explicit z share, transposed, through its lag
+          r += A.tkw1 * (g.lzd[k] * cur.pc + g.lztl[k] * pzm + g.lzth[k] * cur.pzp);
       }
       zm = zc;
       zc = zp;
       w0 = w1;
+      if constexpr (EXPZ) pzm = cur.pc;
     }
     if (MODE == BWD0) {
       if (act && k < nz) stb(A.out + k * nxy, oc, r);
@@ -300,7 +330,7 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
     }
     if (kk + 1 < L) {
       if (PFD == 0) {
-        cur = fetch(k + 1);
+        cur = fetch(kk + 1);
       } else {
         cur = n1;
         if (PFD == 2) n1 = n2;
@@ -372,6 +402,24 @@ struct StepLayout {
   static constexpr int prefetch = sizeof(T) == 8 ? MR_PFD64 : MR_PFD32;  // levels whose loads run ahead of the arithmetic
 };
 
+// Compile-time variants: side walls, explicit z share (never for the seed solve).
+template <typename T, int LL, int MODE, int R, int MB, int PF>
+void launch_variant(bool walls, bool expz, dim3 grid, dim3 block, hipStream_t s, const LineArgs<T>& a) {
+  if constexpr (MODE != SEED) {
+    if (expz) {
+      if (walls)
+        hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, true, true>), grid, block, 0, s, a);
+      else
+        hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, false, true>), grid, block, 0, s, a);
+      return;
+    }
+  }
+  if (walls)
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, true, false>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, false, false>), grid, block, 0, s, a);
+}
+
 template <typename T, int MODE>
 hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   constexpr int rows = StepLayout<T>::rows, cols = kWave / rows;
@@ -381,13 +429,12 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   a.band = StepLayout<T>::band > 0 && StepLayout<T>::band < ntx ? StepLayout<T>::band : ntx;
   const dim3 grid((unsigned)(ntx * nty));
   const dim3 block(kWave, c->nch);
+  const bool walls = a.wx || a.wy;
+  const bool expz = MODE != SEED && c->z_explicit > 0.0;
   switch (c->L) {
-#define MR_CASE(LL)                                                                        \
-  case LL:                                                                                 \
-    if (a.wx || a.wy)                                                                      \
-      hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf, true>), grid, block, 0, s, a);  \
-    else                                                                                   \
-      hipLaunchKernelGGL((line_kernel<T, LL, MODE, rows, mb, pf, false>), grid, block, 0, s, a); \
+#define MR_CASE(LL)                                                                             \
+  case LL:                                                                                      \
+    launch_variant<T, LL, MODE, rows, mb, pf>(walls, expz, grid, block, s, a);                  \
     break;
     MR_CASE(8)
     MR_CASE(16)
@@ -431,6 +478,7 @@ hipError_t step_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* thp, const
   a.ac = (T)alpha_cur(kind);
   a.tau = (T)c->tau[kind];
   a.tk = (T)(c->tau[kind] * c->kappa);
+  a.tkw = (T)(c->tau[kind] * c->kappa * c->z_explicit);
   return launch_line<T, FWD>(c, a, s);
 }
 
@@ -461,10 +509,12 @@ hipError_t bwd_t(mr_ctx* c, const Geom<T>& g, int64_t n, const void* mun, const 
   a.ac = (T)alpha_cur(kind);
   a.tau = (T)c->tau[kind];
   a.tk = (T)(c->tau[kind] * c->kappa);
+  a.tkw = (T)(c->tau[kind] * c->kappa * c->z_explicit);
   if (mun) {
     const int k1 = step_kind(n + 1, c->n_avg);
     a.ap1 = (T)alpha_prev(k1);
     a.tk1 = (T)(c->tau[k1] * c->kappa);
+    a.tkw1 = (T)(c->tau[k1] * c->kappa * c->z_explicit);
   }
   if (n == 0) return launch_line<T, BWD0>(c, a, s);
   a.z = c->zt[step_kind(n - 1, c->n_avg)];

@@ -167,6 +167,8 @@ int check_desc(const mr_desc* d, Problem& P) {
   if (!std::isfinite(d->t_bot) || !std::isfinite(d->t_top)) return MR_EINVAL;
   if ((d->side_x != MR_PERIODIC && d->side_x != MR_WALLS) || (d->side_y != MR_PERIODIC && d->side_y != MR_WALLS))
     return MR_EINVAL;
+  // explicit z share: up to 1/2 the z part stays unconditionally stable
+  if (!(d->z_explicit >= 0.0 && d->z_explicit <= 0.5)) return MR_EINVAL;
   int st;
   if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
   if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
@@ -298,11 +300,12 @@ vector<double> inv(const vector<double>& v) {
 
 struct GeomOffsets {
   size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz, zlo, zhi;
+  size_t lzl, lzd, lzh, lztl, lzth;
 };
 
 template <typename T>
-GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, const vector<int>* idx,
-                      int npad) {
+GeomOffsets pack_geom(Packer& pk, const Problem& P, const mr_desc* d, const vector<double>* R,
+                      const vector<int>* idx, int npad) {
   GeomOffsets o;
   o.hx = pk.put(cast<T>(P.x.h));
   o.ihx = pk.put(cast<T>(inv(P.x.h)));
@@ -332,6 +335,29 @@ GeomOffsets pack_geom(Packer& pk, const Problem& P, const vector<double>* R, con
   }
   o.zlo = pk.put(cast<T>(lo));
   o.zhi = pk.put(cast<T>(hi));
+  // Lz0 rows and their transpose (a Dirichlet wall adds to the diagonal; its
+  // wall value is the separate source b_z)
+  const int nz = P.z.n;
+  const vector<double>& h = P.z.h;
+  const vector<double>& dc = P.z.dc;
+  vector<double> zl(npad, 0.0), zd(npad, 0.0), zh(npad, 0.0), ztl(npad, 0.0), zth(npad, 0.0);
+  for (int k = 0; k < nz; ++k) {
+    zl[k] = k > 0 ? 1.0 / (h[k] * dc[k]) : 0.0;
+    zh[k] = k < nz - 1 ? 1.0 / (h[k] * dc[k + 1]) : 0.0;
+    double dg = -(zl[k] + zh[k]);
+    if (k == 0 && d->bc_bot == MR_DIRICHLET) dg -= 1.0 / (h[0] * dc[0]);
+    if (k == nz - 1 && d->bc_top == MR_DIRICHLET) dg -= 1.0 / (h[nz - 1] * dc[nz]);
+    zd[k] = dg;
+  }
+  for (int k = 0; k < nz; ++k) {
+    ztl[k] = k > 0 ? zh[k - 1] : 0.0;
+    zth[k] = k < nz - 1 ? zl[k + 1] : 0.0;
+  }
+  o.lzl = pk.put(cast<T>(zl));
+  o.lzd = pk.put(cast<T>(zd));
+  o.lzh = pk.put(cast<T>(zh));
+  o.lztl = pk.put(cast<T>(ztl));
+  o.lzth = pk.put(cast<T>(zth));
   return o;
 }
 
@@ -345,6 +371,8 @@ mr::Geom<T> geom_ptrs(char* base, const GeomOffsets& o) {
   g.Rx = (const T*)(base + o.Rx); g.Ry = (const T*)(base + o.Ry); g.Rz = (const T*)(base + o.Rz);
   g.sx = (const int*)(base + o.sx); g.sy = (const int*)(base + o.sy); g.sz = (const int*)(base + o.sz);
   g.zlo = (const T*)(base + o.zlo); g.zhi = (const T*)(base + o.zhi);
+  g.lzl = (const T*)(base + o.lzl); g.lzd = (const T*)(base + o.lzd); g.lzh = (const T*)(base + o.lzh);
+  g.lztl = (const T*)(base + o.lztl); g.lzth = (const T*)(base + o.lzth);
   return g;
 }
 
@@ -428,7 +456,7 @@ int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, 
   if (st != MR_OK) return st;
   if (n < 0) return MR_EINVAL;
   const double tau = kind_tau(mr::step_kind(n, desc->n_avg), desc->dt);
-  z_system(P.z, desc, tau * P.kappa, sub, diag, sup, bz);
+  z_system(P.z, desc, tau * P.kappa * (1.0 - desc->z_explicit), sub, diag, sup, bz);
   if (tau_out) *tau_out = tau;
   return MR_OK;
 }
@@ -448,8 +476,8 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     if ((st = refinement_table(*axes[a], R[a], idx[a], start[a])) != MR_OK) return st;
 
   Packer pk;
-  GeomOffsets o64 = pack_geom<double>(pk, P, R, idx, nch * L);
-  GeomOffsets o32 = pack_geom<float>(pk, P, R, idx, nch * L);
+  GeomOffsets o64 = pack_geom<double>(pk, P, desc, R, idx, nch * L);
+  GeomOffsets o32 = pack_geom<float>(pk, P, desc, R, idx, nch * L);
   ZOffsets zfo[mr::NKINDS], zto[mr::NKINDS];
   double taus[mr::NKINDS];
   const int nz = P.z.n;
@@ -458,7 +486,8 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     const double tau = kind_tau(kind, desc->dt);
     taus[kind] = tau;
     const double tk = tau * P.kappa;
-    z_system(P.z, desc, tk, sub.data(), diag.data(), sup.data(), bz.data());
+    // the implicit share (1 - w) of the z diffusion; the wall source stays whole
+    z_system(P.z, desc, tk * (1.0 - desc->z_explicit), sub.data(), diag.data(), sup.data(), bz.data());
     ZHost zh, th;
     if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
     zh.tkb.assign((size_t)nch * L, 0.0);
@@ -488,6 +517,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   c->bc_bot = desc->bc_bot; c->bc_top = desc->bc_top; c->n_avg = desc->n_avg;
   c->wx = desc->side_x == MR_WALLS;
   c->wy = desc->side_y == MR_WALLS;
+  c->z_explicit = desc->z_explicit;
   c->L = L; c->nch = nch;
   for (int k = 0; k < mr::NKINDS; ++k) c->tau[k] = taus[k];
   {

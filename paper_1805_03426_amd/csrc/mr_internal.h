@@ -40,6 +40,15 @@ struct Geom {
   const int* sz;  // [ncz][3]
   const T* zlo;   // [nch*L] 1 where z level k has an interior face below (0 < k < nz), else 0
   const T* zhi;   // [nch*L] 1 where z level k has an interior face above (k < nz-1), else 0
+  // Lz0 (vertical diffusion per unit volume without the Dirichlet wall source):
+  // row k = lzl[k] level k-1 + lzd[k] level k + lzh[k] level k+1; its transpose
+  // has lztl[k] = lzh[k-1] and lzth[k] = lzl[k+1] off the diagonal.  [nch*L],
+  // zero on the padding rows of the line solver.
+  const T* lzl;
+  const T* lzd;
+  const T* lzh;
+  const T* lztl;
+  const T* lzth;
 };
 
 // Factors of one tridiagonal system (I - tau kappa Lz or its transpose) for
@@ -65,6 +74,7 @@ struct mr_ctx {
   double kappa, dt, ra, pr, t_bot, t_top;
   int bc_bot, bc_top, n_avg;
   int wx, wy;                      // x / y bounded by adiabatic no-slip walls (else periodic)
+  double z_explicit;               // w: share of the z diffusion explicit on the lagged level
   int device;
   int last_err;
   int L, nch;                      // z chunk length and count of the line solver

@@ -99,6 +99,21 @@ def test_host_z_system_matches_oracle(bc):
         np.testing.assert_allclose(bz, obz, rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("wz", [0.5, 0.3])
+def test_host_z_system_with_explicit_share(wz):
+    """The solved system keeps the implicit share (1 - w) of the z diffusion;
+    the wall source b_z is unchanged."""
+    (d, keep), (xf, yf, zf) = _desc(gamma=2.5, n_avg=4, t_bot=0.8, t_top=0.1)
+    d.z_explicit = wz
+    g = O.Grid(xf, yf, zf, (2, 3, 2))
+    p = O.ScalarParams.from_ra_pr(1e6, 4.38, dt=1e-3, n_avg=4, t_bot=0.8, t_top=0.1, z_explicit=wz)
+    for n in (0, 1, 3):
+        sub, diag, sup, bz, tau = host_z_system(d, n)
+        osub, odiag, osup, obz = O.z_matrix(g, tau * p.kappa * (1.0 - wz), p)
+        for a, b in ((sub, osub), (diag, odiag), (sup, osup), (bz, obz)):
+            np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)
+
+
 def _init_status(**over):
     """mr_init status for a descriptor with one field changed (checked on the
     host before any HIP call)."""
@@ -112,6 +127,7 @@ def _init_status(**over):
 @pytest.mark.parametrize("field,value", [
     ("mx", 0), ("ncz", 0), ("ncx", 2), ("dt", 0.0), ("dt", -1.0), ("ra", 0.0), ("pr", -2.0),
     ("bc_bot", 7), ("precision", 5), ("n_avg", -1), ("dt", float("nan")), ("side_x", 2), ("side_y", -1),
+    ("z_explicit", -0.1), ("z_explicit", 0.6), ("z_explicit", float("nan")),
 ])
 def test_init_rejects_bad_descriptor(field, value):
     assert _init_status(**{field: value}) == _lib.MR_EINVAL
