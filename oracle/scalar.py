@@ -6,7 +6,10 @@ step every N_p steps (Eq. 7), and the heat-flux Nusselt number (Eq. 22).
 
 Readings (each also listed in the design notes):
 * face value of the advected scalar: second-order central, the arithmetic
-  mean of the two neighbouring cells (the paper's code is fourth order);
+  mean of the two neighbouring cells, by default; or fourth order as in the
+  paper's code (Sec. 2.2), read as the value at the face of the polynomial
+  whose means over the stencil cells equal their values (two cells on each
+  side of the face; on a walled axis only the cells that exist);
 * diffusion: x and y explicit on the lagged level n-1 as in Eq. 6; the z part
   moved to the new level n+1 and solved line by line (backward Euler over the
   step's time span tau), which keeps the wall-clustered z grid stable;
@@ -50,6 +53,7 @@ class ScalarParams:
     ra: float = 1.0              # Ra and Pr enter Nu through (Ra Pr)^(1/2)
     pr: float = 1.0
     z_explicit: float = 0.0      # w: share of the z diffusion taken explicit on the lagged level
+    face_order: int = 2          # face value of the advected scalar: 2 (mean) or 4
 
     @staticmethod
     def from_ra_pr(ra, pr, dt, **kw):
@@ -109,6 +113,83 @@ def _to_cells(s_lo, s_hi, axis, periodic):
     return np.take(s_hi, np.arange(n), axis=axis) + np.take(s_lo, np.arange(1, n + 1), axis=axis)
 
 
+# ------------------------------------------------------- face interpolation
+def _interval_means(a, b, npow):
+    """Means over [a, b] of x^q, q = 0..npow-1."""
+    q = np.arange(npow)
+    return (b ** (q + 1) - a ** (q + 1)) / ((q + 1) * (b - a))
+
+
+def face_weights(ax, order):
+    """Stencils of the face value along one axis: (cells, weights), shape (nf, 4).
+
+    The value on face f is sum_s weights[f, s] * theta[cells[f, s]]; unused
+    slots have weight 0.  Faces: periodic axis n faces (face i between cells
+    i-1 and i); walled axis n+1 faces, whose two wall faces get zero weights.
+    order 2: the mean of the two cells.  order 4 (Sec. 2.2, fourth-order face
+    values): the stencil is the two cells on each side of the face -- on a
+    periodic axis wrapped around with the period added to their coordinates,
+    on a walled axis only the cells that exist (three next to a wall cell, two
+    when the axis has two cells) -- and the face value is the value at the
+    face of the polynomial (degree = cells - 1) whose mean over every stencil
+    cell equals that cell's value."""
+    n, f = ax.n, ax.faces
+    nf = n if ax.periodic else n + 1
+    cells = np.zeros((nf, 4), dtype=np.int64)
+    wts = np.zeros((nf, 4))
+    for face in range(nf):
+        if not ax.periodic and (face == 0 or face == n):
+            continue
+        if order == 2:
+            lo, hi = face - 1, face
+        elif order == 4:
+            lo, hi = face - 2, face + 1
+            if not ax.periodic:
+                lo, hi = max(lo, 0), min(hi, n - 1)
+        else:
+            raise ValueError("face order must be 2 or 4")
+        xf = f[face]
+        h = ax.h[face % n]                       # length scale of the local solve
+        rows, idx = [], []
+        for c in range(lo, hi + 1):
+            wrap, cell = divmod(c, n)            # wrap = periods crossed (periodic axes only)
+            shift = wrap * ax.length
+            a = (f[cell] + shift - xf) / h
+            b = (f[cell + 1] + shift - xf) / h
+            rows.append((a, b))
+            idx.append(cell)
+        m = len(rows)
+        A = np.array([_interval_means(a, b, m) for a, b in rows])
+        # face value = coefficient of x^0 = e_0 . A^-1 theta  ->  weights = A^-T e_0
+        e0 = np.zeros(m)
+        e0[0] = 1.0
+        wts[face, :m] = np.linalg.solve(A.T, e0)
+        cells[face, :m] = idx
+    return cells, wts
+
+
+def face_values(ax, q, axis, order):
+    """Face values of q along ``axis`` (faces first as in ``face_weights``)."""
+    cells, wts = face_weights(ax, order)
+    q0 = np.moveaxis(q, axis, 0)
+    out = np.zeros((cells.shape[0],) + q0.shape[1:])
+    for s in range(4):
+        out += wts[:, s].reshape((-1,) + (1,) * (q0.ndim - 1)) * q0[cells[:, s]]
+    return np.moveaxis(out, 0, axis)
+
+
+def face_values_transpose(ax, t, axis, order):
+    """Transpose of ``face_values``: face quantities t -> cells."""
+    cells, wts = face_weights(ax, order)
+    t0 = np.moveaxis(t, axis, 0)
+    out = np.zeros((ax.n,) + t0.shape[1:])
+    for face in range(cells.shape[0]):
+        for s in range(4):
+            if wts[face, s] != 0.0:
+                out[cells[face, s]] += wts[face, s] * t0[face]
+    return np.moveaxis(out, 0, axis)
+
+
 # ------------------------------------------------------------------ operators
 def _areas(g):
     ax = g.y.h[None, :, None] * g.z.h[:, None, None]       # x-face areas hy*hz
@@ -117,9 +198,12 @@ def _areas(g):
     return ax, ay, az
 
 
-def advection(g, th, u, v, w):
+def advection(g, th, u, v, w, order=2):
     """C(theta) = -(1/V) sum of outward fluxes u_f A_f theta_f, theta_f = mean of the
-    two cells (Eq. 5, convective term); no flux through any wall."""
+    two cells (Eq. 5, convective term), or the fourth-order face value of
+    ``face_weights`` with order=4; no flux through any wall."""
+    if order == 4:
+        return _advection4(g, th, u, v, w)
     ax, ay, az = _areas(g)
     px, py = g.x.periodic, g.y.periodic
     if px and py:
@@ -133,6 +217,16 @@ def advection(g, th, u, v, w):
     nz = th.shape[0]
     fz = np.zeros((nz + 1,) + th.shape[1:])
     fz[1:nz] = w[1:nz] * 0.5 * (th[:-1] + th[1:]) * az[None]
+    net = _net(fx, 2, px) + _net(fy, 1, py) + (fz[1:] - fz[:-1])
+    return -net / g.vol()
+
+
+def _advection4(g, th, u, v, w):
+    ax, ay, az = _areas(g)
+    px, py = g.x.periodic, g.y.periodic
+    fx = _open(u * face_values(g.x, th, 2, 4) * ax, 2, px)
+    fy = _open(v * face_values(g.y, th, 1, 4) * ay, 1, py)
+    fz = _open(w * face_values(g.z, th, 0, 4) * az[None], 0, False)
     net = _net(fx, 2, px) + _net(fy, 1, py) + (fz[1:] - fz[:-1])
     return -net / g.vol()
 
@@ -223,7 +317,7 @@ def scalar_step(g, p, n, th_prev, th_cur, u, v, w):
     th_prev is ignored at n = 0."""
     tau, ap, ac, _ = step_kind(n, p.n_avg, p.dt)
     lag = th_cur if n == 0 else th_prev
-    r = ac * th_cur + tau * (advection(g, th_cur, u, v, w) + p.kappa * lap_h(g, lag))
+    r = ac * th_cur + tau * (advection(g, th_cur, u, v, w, p.face_order) + p.kappa * lap_h(g, lag))
     if n > 0:
         r = r + ap * th_prev
     wz = p.z_explicit
@@ -289,9 +383,12 @@ def _lap_h_transpose(g, mu):
     return out
 
 
-def _advection_transpose(g, mu, u, v, w):
+def _advection_transpose(g, mu, u, v, w, order=2):
     """C_u^T mu: each face f (cells L, R) gives s_f = u_f A_f (q_R - q_L)/2 to both
-    cells; wall faces give nothing."""
+    cells (order 2), or s_f times its stencil weights to its stencil cells
+    (order 4); wall faces give nothing."""
+    if order == 4:
+        return _advection4_transpose(g, mu, u, v, w)
     ax, ay, az = _areas(g)
     q = mu / g.vol()
     nz = mu.shape[0]
@@ -310,10 +407,33 @@ def _advection_transpose(g, mu, u, v, w):
     return out
 
 
-def _advection_velocity_transpose(g, mu, th):
-    """Gradient of sum(mu * C_u(theta)) w.r.t. every dense face velocity:
-    A_f (theta_L + theta_R)/2 (q_R - q_L); zero on every wall face."""
+def _advection4_transpose(g, mu, u, v, w):
+    """sum(mu * C(theta)) = sum_f s_f theta_f with s_f = u_f A_f (q_R - q_L), so
+    C^T mu is the transposed face interpolation of s."""
     ax, ay, az = _areas(g)
+    q = mu / g.vol()
+    px, py = g.x.periodic, g.y.periodic
+    out = np.zeros_like(mu)
+    for axis, vel, a, per, axo in ((2, u, ax, px, g.x), (1, v, ay, py, g.y), (0, w, az[None], False, g.z)):
+        lo, hi = _sides(q, axis, per)
+        sf = _open(vel * a * (hi - lo), axis, per)
+        out = out + face_values_transpose(axo, sf, axis, 4)
+    return out
+
+
+def _advection_velocity_transpose(g, mu, th, order=2):
+    """Gradient of sum(mu * C_u(theta)) w.r.t. every dense face velocity:
+    A_f theta_f (q_R - q_L) with theta_f the face value of the step's order;
+    zero on every wall face."""
+    ax, ay, az = _areas(g)
+    if order == 4:
+        q = mu / g.vol()
+        px, py = g.x.periodic, g.y.periodic
+        grads = []
+        for axis, a, per, axo in ((2, ax, px, g.x), (1, ay, py, g.y), (0, az[None], False, g.z)):
+            lo, hi = _sides(q, axis, per)
+            grads.append(_open(a * face_values(axo, th, axis, 4) * (hi - lo), axis, per))
+        return tuple(grads)
     q = mu / g.vol()
     px, py = g.x.periodic, g.y.periodic
     if px and py:
@@ -353,13 +473,13 @@ def step_vjp(g, p, n, th_cur, u, v, w, lam_next):
     lh = (tau * p.kappa) * _lap_h_transpose(g, mu)
     if wz:
         lh = lh + (tau * p.kappa * wz) * lz0_transpose(g, p, mu)
-    g_cur = ac * mu + tau * _advection_transpose(g, mu, u, v, w)
+    g_cur = ac * mu + tau * _advection_transpose(g, mu, u, v, w, p.face_order)
     if n == 0:
         g_cur = g_cur + lh
         g_prev = np.zeros_like(mu)
     else:
         g_prev = ap * mu + lh
-    gu, gv, gw = _advection_velocity_transpose(g, mu, th_cur)
+    gu, gv, gw = _advection_velocity_transpose(g, mu, th_cur, p.face_order)
     return g_prev, g_cur, tau * gu, tau * gv, tau * gw
 
 
