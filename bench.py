@@ -48,7 +48,7 @@ def kernel_source_hash():
     shared header and the host tables and chunk choice), to tell whether the
     committed counters of that kernel are stale."""
     h = hashlib.sha256()
-    for name in ("k_step.hip", "mr_internal.h", "mr_api.hip"):
+    for name in ("line_kernel.h", "k_line_fwd.hip", "k_step.hip", "mr_internal.h", "mr_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_1805_03426_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -293,13 +293,14 @@ def walls_times(w):
                 refine_ms=ref_ms)
 
 
-def zweight_times(w, z_explicit=0.5):
-    """The workload's FP64 step with a share w of the z diffusion explicit on
-    the lagged level (w = 1/2, Crank-Nicolson across the step span): mean
-    kernel time and % of HBM peak (the same algorithmic 48 B per cell)."""
+def variant_step_times(w, **variant):
+    """The workload's FP64 step in a variant of the method (``variant`` goes to
+    the Context: z_explicit = 1/2 for the Crank-Nicolson z share, face_order = 4
+    for fourth-order face values): mean kernel time and % of HBM peak (the same
+    algorithmic 48 B per cell)."""
     from paper_1805_03426_amd.context import Context
     d = inputs.workload_inputs(w)
-    ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, z_explicit=z_explicit)
+    ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, **variant)
     U, V, W = (torch.from_numpy(d[k]).to("cuda", torch.float64) for k in ("U", "V", "W"))
     u, v, w_ = ctx.interpolate_velocity(U, V, W)
     ring = [torch.from_numpy(d["theta0"]).to("cuda", torch.float64)] + [ctx.empty(ctx.shape_cell) for _ in range(3)]
@@ -313,8 +314,7 @@ def zweight_times(w, z_explicit=0.5):
 
     ms = _event_ms(step, reps=20, warmup=3)
     ctx.close()
-    return dict(z_explicit=z_explicit, step_kernel_ms=ms,
-                step_hbm_frac_alg=48 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    return dict(variant, step_kernel_ms=ms, step_hbm_frac_alg=48 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -396,7 +396,10 @@ def main():
         extras["walls_xy"] = walls_times(w)
         torch.cuda.empty_cache()
         print("bench: step with an explicit z share", file=sys.stderr, flush=True)
-        extras["z_explicit"] = zweight_times(w)
+        extras["z_explicit"] = variant_step_times(w, z_explicit=0.5)
+        torch.cuda.empty_cache()
+        print("bench: step with fourth-order faces", file=sys.stderr, flush=True)
+        extras["face_order4"] = variant_step_times(w, face_order=4)
         torch.cuda.empty_cache()
         print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
         extras["fp32_large"] = large_fp32_step_times()

@@ -89,6 +89,10 @@ typedef struct {
   double z_explicit;       /* w in [0, 1/2]: share of the z diffusion taken explicit on the
                               lagged level (0 = fully implicit, 1/2 = Crank-Nicolson across
                               the step's time span; a reading of Sec. 2.2's implicit z) */
+  int32_t face_order;      /* face value of the advected scalar: 2 (or 0) = mean of the two cells,
+                              4 = fourth order (Sec. 2.2; the polynomial whose means over the
+                              two cells on each side of the face equal their values, only the
+                              cells that exist next to a wall); 4 needs uniform x and y widths */
 } mr_desc;
 
 /* Nusselt summary of one scalar field (Eq. 22, instantaneous). */
@@ -268,6 +272,12 @@ int mr_host_refinement_table(const mr_desc* desc, int32_t axis, double* R_out, i
  * *tau_out (w = desc->z_explicit). */
 int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, double* sup,
                      double* bz, double* tau_out);
+
+/* Host-only: the fourth-order face weights of the z axis (Sec. 2.2) that the
+ * step uses with face_order 4: w_out receives (nz+1)*4 doubles, face f's
+ * weights for the cells f-2, f-1, f, f+1 (zero for the wall faces and for
+ * cells beyond a wall). */
+int mr_host_z_face_weights(const mr_desc* desc, double* w_out);
 
 /* Dense sizes of a context and its precision. */
 int mr_get_dims(const mr_ctx* ctx, int32_t* nx, int32_t* ny, int32_t* nz, int32_t* precision);

@@ -22,7 +22,7 @@ EXPORTS = [
     "mr_velocity_grad", "mr_nusselt", "mr_copy_probe", "mr_host_refinement_table",
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
     "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
-    "mr_coarse_step",
+    "mr_coarse_step", "mr_host_z_face_weights",
 ]
 
 
@@ -39,6 +39,7 @@ class mr_desc(ctypes.Structure):
         ("precision", c_int32),
         ("side_x", c_int32), ("side_y", c_int32),
         ("z_explicit", c_double),
+        ("face_order", c_int32),
     ]
 
 
@@ -95,6 +96,7 @@ def lib():
         "mr_host_z_system": (c_int, [POINTER(mr_desc), c_int64, POINTER(c_double),
                                      POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double)]),
+        "mr_host_z_face_weights": (c_int, [POINTER(mr_desc), POINTER(c_double)]),
         "mr_get_dims": (c_int, [P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                 POINTER(c_int32)]),
         "mr_status_string": (c_char_p, [c_int]),

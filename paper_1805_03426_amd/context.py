@@ -22,11 +22,12 @@ _SIDE = {"periodic": _lib.MR_PERIODIC, "walls": _lib.MR_WALLS}
 
 def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot="dirichlet",
               bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic",
-              z_explicit=0.0):
+              z_explicit=0.0, face_order=2):
     """Build an ``mr_desc``; returns (desc, keepalive) -- keep the second alive
     while the descriptor is in use (it owns the face arrays).  side_x / side_y:
     "periodic" or "walls" (adiabatic no-slip side walls); z_explicit: share w of
-    the z diffusion taken explicit on the lagged level (0 to 1/2)."""
+    the z diffusion taken explicit on the lagged level (0 to 1/2); face_order:
+    2 (mean of the two cells) or 4 (fourth-order face values, uniform x and y)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
     mx, my, mz = (int(a) for a in m)
     n = [f.size - 1 for f in faces]
@@ -45,6 +46,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     d.precision = _PREC[precision]
     d.side_x, d.side_y = _SIDE[side_x], _SIDE[side_y]
     d.z_explicit = float(z_explicit)
+    d.face_order = int(face_order)
     return d, faces
 
 
@@ -72,6 +74,16 @@ def host_z_system(desc, n):
     return (*arrs, tau.value)
 
 
+def host_z_face_weights(desc):
+    """(nz+1, 4) fourth-order face weights of the z axis, face f's for the cells
+    f-2..f+1, as the step uses them with face_order 4 (host only)."""
+    nz = desc.ncz * desc.mz
+    w = np.zeros((nz + 1, 4))
+    check(lib().mr_host_z_face_weights(byref(desc), w.ctypes.data_as(ctypes.POINTER(c_double))),
+          "mr_host_z_face_weights")
+    return w
+
+
 def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -81,11 +93,11 @@ class Context:
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
                  bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
-                 side_y="periodic", z_explicit=0.0):
+                 side_y="periodic", z_explicit=0.0, face_order=2):
         if not torch.cuda.is_available():
             raise RuntimeError("the multiple-resolution library needs a HIP GPU")
         desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision,
-                               side_x, side_y, z_explicit)
+                               side_x, side_y, z_explicit, face_order)
         self.desc, self._keep = desc, keep
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._ctx = c_void_p()

@@ -52,6 +52,51 @@ int build_axis(const double* faces, int n, int m, bool periodic, Axis& ax) {
   return MR_OK;
 }
 
+// True when the widths of the axis are equal to within 1e-13 relative.
+bool uniform_axis(const Axis& ax) {
+  const double h0 = ax.h[0];
+  for (double h : ax.h)
+    if (fabs(h - h0) > 1e-13 * h0) return false;
+  return true;
+}
+
+// Fourth-order face weights of a walled axis (Sec. 2.2): face f (0 < f < n)
+// takes the two cells on each side that exist, cells lo..hi.  The face value
+// of the polynomial whose cell means equal the cell values is the derivative
+// at the face of the polynomial that interpolates the primitive
+// P(e_j) = sum_{s<j} h_s theta_s at the stencil's edges e_0..e_m, so cell s
+// gets h_s * sum_{j>s} L_j'(x_f), L_j the Lagrange basis on the edges.
+// Returns (n+1)*4 weights, face f's for cells f-2..f+1 (zero rows for walls).
+vector<double> face_weights4(const Axis& ax) {
+  const int n = ax.n;
+  vector<double> w((size_t)(n + 1) * 4, 0.0);
+  for (int f = 1; f < n; ++f) {
+    const int lo = std::max(f - 2, 0), hi = std::min(f + 1, n - 1);
+    const int m = hi - lo + 1;
+    const double xf = ax.f[f], sc = ax.h[f];
+    double e[5];
+    for (int q = 0; q <= m; ++q) e[q] = (ax.f[lo + q] - xf) / sc;
+    double dl[5];   // L_j'(0)
+    for (int jj = 0; jj <= m; ++jj) {
+      double sum = 0.0;
+      for (int l = 0; l <= m; ++l) {
+        if (l == jj) continue;
+        double prod = 1.0 / (e[jj] - e[l]);
+        for (int r = 0; r <= m; ++r)
+          if (r != jj && r != l) prod *= (0.0 - e[r]) / (e[jj] - e[r]);
+        sum += prod;
+      }
+      dl[jj] = sum;
+    }
+    for (int q = 0; q < m; ++q) {
+      double acc = 0.0;
+      for (int jj = q + 1; jj <= m; ++jj) acc += dl[jj];
+      w[(size_t)f * 4 + (lo + q - (f - 2))] = (e[q + 1] - e[q]) * acc;
+    }
+  }
+  return w;
+}
+
 // Means of 1, x, x^2 over [a, b]: a row of A (Eq. 15) or A_s (Eq. 18).
 void interval_means(double a, double b, double* row) {
   row[0] = 1.0;
@@ -169,10 +214,13 @@ int check_desc(const mr_desc* d, Problem& P) {
     return MR_EINVAL;
   // explicit z share: up to 1/2 the z part stays unconditionally stable
   if (!(d->z_explicit >= 0.0 && d->z_explicit <= 0.5)) return MR_EINVAL;
+  if (d->face_order != 0 && d->face_order != 2 && d->face_order != 4) return MR_EINVAL;
   int st;
   if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
   if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
   if ((st = build_axis(d->zf, (int)nz, d->mz, false, P.z)) != MR_OK) return st;
+  // fourth-order faces: the kernels use the uniform-width weights in x and y
+  if (d->face_order == 4 && (!uniform_axis(P.x) || !uniform_axis(P.y))) return MR_EINVAL;
   P.kappa = 1.0 / sqrt(d->ra * d->pr);
   // explicit x/y diffusion: the leapfrog step is forward Euler over 2 dt
   const double hxm = *std::min_element(P.x.h.begin(), P.x.h.end());
@@ -300,7 +348,7 @@ vector<double> inv(const vector<double>& v) {
 
 struct GeomOffsets {
   size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz, zlo, zhi;
-  size_t lzl, lzd, lzh, lztl, lzth;
+  size_t lzl, lzd, lzh, lztl, lzth, c4z, c4zt;
 };
 
 template <typename T>
@@ -358,6 +406,18 @@ GeomOffsets pack_geom(Packer& pk, const Problem& P, const mr_desc* d, const vect
   o.lzh = pk.put(cast<T>(zh));
   o.lztl = pk.put(cast<T>(ztl));
   o.lzth = pk.put(cast<T>(zth));
+  // fourth-order z faces, padded: faces 0..npad, cells per level 0..npad-1
+  const vector<double> w4 = face_weights4(P.z);
+  vector<double> c4((size_t)(npad + 1) * 4, 0.0), c4t((size_t)npad * 4, 0.0);
+  for (int f = 0; f <= nz; ++f)
+    for (int q = 0; q < 4; ++q) c4[(size_t)f * 4 + q] = w4[(size_t)f * 4 + q];
+  for (int k = 0; k < nz; ++k)
+    for (int q = 0; q < 4; ++q) {
+      const int f = k - 1 + q;   // cell k is slot 3 - q of face k - 1 + q
+      if (f >= 0 && f <= nz) c4t[(size_t)k * 4 + q] = w4[(size_t)f * 4 + (3 - q)];
+    }
+  o.c4z = pk.put(cast<T>(c4));
+  o.c4zt = pk.put(cast<T>(c4t));
   return o;
 }
 
@@ -373,6 +433,7 @@ mr::Geom<T> geom_ptrs(char* base, const GeomOffsets& o) {
   g.zlo = (const T*)(base + o.zlo); g.zhi = (const T*)(base + o.zhi);
   g.lzl = (const T*)(base + o.lzl); g.lzd = (const T*)(base + o.lzd); g.lzh = (const T*)(base + o.lzh);
   g.lztl = (const T*)(base + o.lztl); g.lzth = (const T*)(base + o.lzth);
+  g.c4z = (const T*)(base + o.c4z); g.c4zt = (const T*)(base + o.c4zt);
   return g;
 }
 
@@ -461,6 +522,16 @@ int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, 
   return MR_OK;
 }
 
+int mr_host_z_face_weights(const mr_desc* desc, double* w_out) {
+  Problem P;
+  int st = check_desc(desc, P);
+  if (st != MR_OK) return st;
+  if (!w_out) return MR_EINVAL;
+  const vector<double> w = face_weights4(P.z);
+  memcpy(w_out, w.data(), w.size() * sizeof(double));
+  return MR_OK;
+}
+
 int mr_init(const mr_desc* desc, mr_ctx** out) {
   if (!out) return MR_EINVAL;
   Problem P;
@@ -518,6 +589,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   c->wx = desc->side_x == MR_WALLS;
   c->wy = desc->side_y == MR_WALLS;
   c->z_explicit = desc->z_explicit;
+  c->face_order = desc->face_order == 4 ? 4 : 2;
   c->L = L; c->nch = nch;
   for (int k = 0; k < mr::NKINDS; ++k) c->tau[k] = taus[k];
   {

@@ -49,6 +49,11 @@ struct Geom {
   const T* lzh;
   const T* lztl;
   const T* lzth;
+  // fourth-order face values in z: c4z[4 f + s] weights face f's value on the
+  // cells f-2+s ([nch*L + 1][4], zero rows for the walls and the padding);
+  // c4zt[4 k + s] is cell k's weight in face k-1+s ([nch*L][4], the transpose)
+  const T* c4z;
+  const T* c4zt;
 };
 
 // Factors of one tridiagonal system (I - tau kappa Lz or its transpose) for
@@ -75,6 +80,7 @@ struct mr_ctx {
   int bc_bot, bc_top, n_avg;
   int wx, wy;                      // x / y bounded by adiabatic no-slip walls (else periodic)
   double z_explicit;               // w: share of the z diffusion explicit on the lagged level
+  int face_order;                  // face value of the advected scalar: 2 or 4
   int device;
   int last_err;
   int L, nch;                      // z chunk length and count of the line solver

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1805_03426_amd import _lib, inputs
-from paper_1805_03426_amd.context import host_refinement_table, host_z_system, make_desc
+from paper_1805_03426_amd.context import host_refinement_table, host_z_face_weights, host_z_system, make_desc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mrscalar.h")
@@ -114,6 +114,40 @@ def test_host_z_system_with_explicit_share(wz):
             np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("nz,gamma", [(1, 0.0), (2, 1.0), (3, 1.0), (12, 2.5), (40, 1.5)])
+def test_host_z_face_weights_match_oracle(nz, gamma):
+    """The library builds its z weights from the derivative of the interpolated
+    primitive (Lagrange basis); the oracle solves the cell-mean system."""
+    (d, keep), (xf, yf, zf) = _desc(nc=(6, 5, nz), m=(2, 3, 1), gamma=gamma, face_order=4)
+    got = host_z_face_weights(d)
+    g = O.Grid(xf, yf, zf, (2, 3, 1))
+    cells, wts = O.scalar.face_weights(g.z, 4)
+    want = np.zeros((nz + 1, 4))
+    for f in range(nz + 1):
+        for s in range(4):
+            if wts[f, s] != 0.0:
+                want[f, cells[f, s] - (f - 2)] += wts[f, s]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("order", [0, 2, 4])
+def test_face_order_accepted(order):
+    (d, keep), _ = _desc(face_order=order)
+    host_z_system(d, 0)
+
+
+def test_face_order4_needs_uniform_x_and_y():
+    rng = np.random.default_rng(3)
+    hy = rng.uniform(0.8, 1.2, 15)
+    yf = np.concatenate([[0.0], np.cumsum(hy)]) / hy.sum()
+    xf = inputs.uniform_faces(12)
+    d, keep = make_desc(xf, yf, inputs.tanh_faces(14, 1.5), (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3, face_order=4)
+    with pytest.raises(_lib.MRError):
+        host_z_system(d, 0)
+    d, keep = make_desc(xf, yf, inputs.tanh_faces(14, 1.5), (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3, face_order=2)
+    host_z_system(d, 0)
+
+
 def _init_status(**over):
     """mr_init status for a descriptor with one field changed (checked on the
     host before any HIP call)."""
@@ -127,7 +161,8 @@ def _init_status(**over):
 @pytest.mark.parametrize("field,value", [
     ("mx", 0), ("ncz", 0), ("ncx", 2), ("dt", 0.0), ("dt", -1.0), ("ra", 0.0), ("pr", -2.0),
     ("bc_bot", 7), ("precision", 5), ("n_avg", -1), ("dt", float("nan")), ("side_x", 2), ("side_y", -1),
-    ("z_explicit", -0.1), ("z_explicit", 0.6), ("z_explicit", float("nan")),
+    ("z_explicit", -0.1), ("z_explicit", 0.6), ("z_explicit", float("nan")), ("face_order", 3),
+    ("face_order", -4),
 ])
 def test_init_rejects_bad_descriptor(field, value):
     assert _init_status(**{field: value}) == _lib.MR_EINVAL
