@@ -83,53 +83,71 @@ __global__ void __launch_bounds__(kWave) max_final(const double* part, int n, do
 }
 
 // ---------------------------------------------------------------- Nusselt
-// partials[(k*P + p)*6 + {conv s,c, grad s,c, mean s,c}]
+// partials[(k*P + p)*6 + {conv s,c, grad s,c, mean s,c}].  Block (p, q) covers
+// the horizontal range p of faces kNuFaces*q .. kNuFaces*q + kNuFaces-1: each
+// lane walks those faces for its cells carrying theta of the level below, so a
+// level is read once per group of faces instead of once per face.
+constexpr int kNuFaces = 4;
+
 template <typename T>
 __global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const double* hx,
                                                   const double* hy, int nx, int ny, int nz, int P,
                                                   int dir_bot, int dir_top, double t_bot,
                                                   double t_top, double* part) {
   __shared__ DD sh[3][256 / kWave];
-  const int k = blockIdx.y;   // face 0..nz (mean of level k for k < nz)
+  const int kf0 = blockIdx.y * kNuFaces;   // first face of the group (faces 0..nz)
   const int p = blockIdx.x;
   const int nxy = nx * ny;
   const int per = (nxy + P - 1) / P;
   const int lo = p * per, hi = min(nxy, lo + per);
-  DD conv{0.0, 0.0}, grad{0.0, 0.0}, mean{0.0, 0.0};
+  DD conv[kNuFaces], grad[kNuFaces], mean[kNuFaces];
+#pragma unroll
+  for (int f = 0; f < kNuFaces; ++f) conv[f] = grad[f] = mean[f] = DD{0.0, 0.0};
   for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
     const int i = e % nx, j = e / nx;
     const double area = hx[i] * hy[j];
-    if (k > 0 && k < nz) {
-      const double a = th[(k - 1) * nxy + e], b = th[k * nxy + e];
-      conv = dd_add(conv, (double)w[k * nxy + e] * (0.5 * (a + b)) * area);
-      grad = dd_add(grad, (b - a) * area);
-    } else if (k == 0) {
-      if (dir_bot) grad = dd_add(grad, ((double)th[e] - t_bot) * area);
-    } else {
-      if (dir_top) grad = dd_add(grad, (t_top - (double)th[(nz - 1) * nxy + e]) * area);
+    double below = kf0 > 0 && kf0 <= nz ? (double)th[(size_t)(kf0 - 1) * nxy + e] : 0.0;
+#pragma unroll
+    for (int f = 0; f < kNuFaces; ++f) {
+      const int k = kf0 + f;
+      if (k > nz) break;
+      const double cur = k < nz ? (double)th[(size_t)k * nxy + e] : 0.0;
+      if (k > 0 && k < nz) {
+        conv[f] = dd_add(conv[f], (double)w[(size_t)k * nxy + e] * (0.5 * (below + cur)) * area);
+        grad[f] = dd_add(grad[f], (cur - below) * area);
+      } else if (k == 0) {
+        if (dir_bot) grad[f] = dd_add(grad[f], (cur - t_bot) * area);
+      } else {
+        if (dir_top) grad[f] = dd_add(grad[f], (t_top - below) * area);
+      }
+      if (k < nz) mean[f] = dd_add(mean[f], cur * area);
+      below = cur;
     }
-    if (k < nz) mean = dd_add(mean, (double)th[k * nxy + e] * area);
   }
-  conv = wave_sum(conv);
-  grad = wave_sum(grad);
-  mean = wave_sum(mean);
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) {
-    sh[0][wv] = conv;
-    sh[1][wv] = grad;
-    sh[2][wv] = mean;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < (int)blockDim.x / kWave; ++q) {
-      conv = dd_merge(conv, sh[0][q]);
-      grad = dd_merge(grad, sh[1][q]);
-      mean = dd_merge(mean, sh[2][q]);
+#pragma unroll
+  for (int f = 0; f < kNuFaces; ++f) {
+    const int k = kf0 + f;
+    if (k > nz) break;
+    DD c = wave_sum(conv[f]), g = wave_sum(grad[f]), m = wave_sum(mean[f]);
+    __syncthreads();   // the previous face's merge has read sh
+    if (lane == 0) {
+      sh[0][wv] = c;
+      sh[1][wv] = g;
+      sh[2][wv] = m;
     }
-    double* o = part + ((size_t)k * P + p) * 6;
-    o[0] = conv.s; o[1] = conv.c;
-    o[2] = grad.s; o[3] = grad.c;
-    o[4] = mean.s; o[5] = mean.c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < (int)blockDim.x / kWave; ++q) {
+        c = dd_merge(c, sh[0][q]);
+        g = dd_merge(g, sh[1][q]);
+        m = dd_merge(m, sh[2][q]);
+      }
+      double* o = part + ((size_t)k * P + p) * 6;
+      o[0] = c.s; o[1] = c.c;
+      o[2] = g.s; o[3] = g.c;
+      o[4] = m.s; o[5] = m.c;
+    }
   }
 }
 
@@ -157,6 +175,7 @@ __global__ void __launch_bounds__(256) nu_final(const double* part, int P, int n
   __shared__ DD scratch[256 / kWave];
   for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
     DD conv{0.0, 0.0}, grad{0.0, 0.0}, mean{0.0, 0.0};
+#pragma unroll 4
     for (int p = 0; p < P; ++p) {
       const double* o = part + ((size_t)k * P + p) * 6;
       conv = dd_merge(conv, DD{o[0], o[1]});
@@ -241,7 +260,7 @@ hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof
   if (c->nz > kNuMaxFaces) return hipErrorInvalidValue;
   hipError_t e = ensure_red(c, sizeof(double) * part);
   if (e != hipSuccess) return e;
-  const dim3 grid(P, c->nz + 1);
+  const dim3 grid(P, (c->nz + 1 + kNuFaces - 1) / kNuFaces);
   const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
   if (c->precision == MR_FP64)
     hipLaunchKernelGGL(nu_partial<double>, grid, dim3(256), 0, s, (const double*)th, (const double*)w,
