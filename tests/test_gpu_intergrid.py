@@ -165,3 +165,29 @@ def test_full_size_rb256_intergrid():
         for k in ("nu_t", "gx2", "gy2", "gz2"):
             assert abs(got[k] - want[k]) <= FP64_TOL * want["nu_t"], k
         print("rb256 Nu_T %.6f (oracle %.6f)" % (got["nu_t"], want["nu_t"]), flush=True)
+
+
+def test_full_size_rb256_coarse_step():
+    """One coarse step of M_t = 4 scalar steps at 256^3 in the benchmark's
+    launch configuration (the second coarse level is the first reversed in z,
+    with zero wall planes): the native loop against the oracle's."""
+    print("case rb256 coarse step full size", flush=True)
+    w = WORKLOADS["rb256-m2-fp64"]
+    d = inputs.workload_inputs(w)
+    g = O.Grid(d["xf"], d["yf"], d["zf"], w.m)
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    U0, V0, W0 = d["U"], d["V"], d["W"]
+    U1, V1, W1 = (np.ascontiguousarray(a[::-1]) for a in (U0, V0, W0))
+    W1[0] = W1[-1] = 0.0
+    mt = 4
+    prev_o, cur_o, tc_o = coarse_step(g, p, 0, mt, d["theta0"], d["theta0"], U0, V0, W0, U1, V1, W1)
+    from paper_1805_03426_amd.context import Context
+    with Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg) as ctx:
+        uvw = (ctx.empty(ctx.shape_cell), ctx.empty(ctx.shape_cell), ctx.empty(ctx.shape_w))
+        ring = [dev(d["theta0"]), ctx.empty(ctx.shape_cell), ctx.empty(ctx.shape_cell)]
+        tc = ctx.empty(ctx.shape_coarse)
+        pi, ci = ctx.coarse_step(0, mt, *(dev(a) for a in (U0, V0, W0, U1, V1, W1)), uvw, ring, 0, 0, tc)
+        assert rel_l2(host(ring[ci]), cur_o) <= FP64_TOL
+        assert rel_max(host(ring[ci]), cur_o) <= FP64_TOL
+        assert rel_l2(host(ring[pi]), prev_o) <= FP64_TOL
+        assert rel_max(host(tc), tc_o) <= FP64_TOL
