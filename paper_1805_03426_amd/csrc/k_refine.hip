@@ -181,8 +181,13 @@ __global__ void __launch_bounds__(256) stage_x(RefArgs<T> A) {
 //      march of U up to its own sub-column (the same operations in the same
 //      order as stage_x).
 // Each dense value is written once, 64 consecutive columns per row; the only
-// HBM reads are the coarse levels (cache-resident halo re-reads).  x and y
-// are periodic, so the y stencil of row J is rows J-1 .. J+1.
+// HBM reads are the coarse levels (cache-resident halo re-reads).  On a
+// periodic axis the halo wraps and the stencil of cell I is I-1 .. I+1; on a
+// walled axis the stencil is the one-sided one of the R tables next to the
+// walls (every stencil cell of the tile then lies in the halo as long as a
+// tile holds at least two cells along that axis, which the launcher ensures),
+// the wall faces are taken as zero, and halo cells beyond a wall are computed
+// but never read.
 constexpr int kFuseCols = 64;
 
 __device__ __forceinline__ int wrapm(int i, int n) {
@@ -316,13 +321,20 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
   const int zr = zon ? t / NXH : 0, zl = zon ? t - zr * NXH : 0;
   const int zI = wrapm(I0 - 1 + zl, ncx), zIp = wrapm(zI + 1, ncx);
   const int zJ = wrapm(J0 - 1 + zr, ncy), zJp = wrapm(zJ + 1, ncy);
+  // walled axes: faces on or beyond a wall carry no velocity (lane selects)
+  const int fI = I0 - 1 + zl, fJ = J0 - 1 + zr;
+  const bool zu0 = A.wx && (fI <= 0 || fI >= ncx), zu1 = A.wx && (fI + 1 <= 0 || fI + 1 >= ncx);
+  const bool zv0 = A.wy && (fJ <= 0 || fJ >= ncy), zv1 = A.wy && (fJ + 1 <= 0 || fJ + 1 >= ncy);
   const T ziHX = g.iHX[zI], ziHY = g.iHY[zJ];
   // stage-x lane roles: column col of the tile, sub-column sub of coarse column Ix
   const int col = t % kFuseCols, grp = t / kFuseCols;
   const int Ix = I0 + col / mx, sub = col - (col / mx) * mx;
   const bool xon = col < CX && Ix < ncx;
   int xloc[3];
-  for (int r = 0; r < 3; ++r) xloc[r] = xon ? wrapm(g.sx[Ix * 3 + r] - (I0 - 1), ncx) : 0;
+  for (int r = 0; r < 3; ++r) {
+    const int p = xon ? g.sx[Ix * 3 + r] - (I0 - 1) : 0;
+    xloc[r] = A.wx ? p : wrapm(p, ncx);
+  }
 
   ZLoad<T, BLEND> cur, nxt;
   if (zon && K0 < K1) z_load<T, BLEND>(A, K0, zI, zIp, zJ, zJp, cur);
@@ -338,10 +350,10 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
     if (zon) {
       T u0[3], u1[3], v0[3], v1[3];
       for (int q = 0; q < 3; ++q) {
-        u0[q] = zb<T, BLEND>(cur.u0[q], cur.u0b[BLEND ? q : 0], s);
-        u1[q] = zb<T, BLEND>(cur.u1[q], cur.u1b[BLEND ? q : 0], s);
-        v0[q] = zb<T, BLEND>(cur.v0[q], cur.v0b[BLEND ? q : 0], s);
-        v1[q] = zb<T, BLEND>(cur.v1[q], cur.v1b[BLEND ? q : 0], s);
+        u0[q] = zu0 ? T(0) : zb<T, BLEND>(cur.u0[q], cur.u0b[BLEND ? q : 0], s);
+        u1[q] = zu1 ? T(0) : zb<T, BLEND>(cur.u1[q], cur.u1b[BLEND ? q : 0], s);
+        v0[q] = zv0 ? T(0) : zb<T, BLEND>(cur.v0[q], cur.v0b[BLEND ? q : 0], s);
+        v1[q] = zv1 ? T(0) : zb<T, BLEND>(cur.v1[q], cur.v1b[BLEND ? q : 0], s);
       }
       T wv = zb<T, BLEND>(cur.wb, cur.wbb, s);
       for (int m = 0; m < mz; ++m) {
@@ -361,11 +373,13 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
       const int l = it % (NXH - 1), rest = it / (NXH - 1);
       const int m = rest % mz, jt = rest / mz;
       T u0[3], u1[3], w0[3], w1[3];
+      // first stencil row of tile row jt (centred unless next to a y wall)
+      const int rs = A.wy ? g.sy[(J0 + jt) * 3] - (J0 - 1) : jt;
       for (int r = 0; r < 3; ++r) {
-        u0[r] = Uz[(m * NYH + jt + r) * NXH + l];
-        u1[r] = Uz[(m * NYH + jt + r) * NXH + l + 1];
-        w0[r] = Wz[(m * NYH + jt + r) * NXH + l];
-        w1[r] = Wz[((m + 1) * NYH + jt + r) * NXH + l];
+        u0[r] = Uz[(m * NYH + rs + r) * NXH + l];
+        u1[r] = Uz[(m * NYH + rs + r) * NXH + l + 1];
+        w0[r] = Wz[(m * NYH + rs + r) * NXH + l];
+        w1[r] = Wz[((m + 1) * NYH + rs + r) * NXH + l];
       }
       const T iHX = tIHX[l], ihz = ihzK[m];
       T vv = Vz[(m * NYH + jt + 1) * NXH + l];
@@ -638,12 +652,19 @@ template <typename T>
 hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, const void* W,
                     const void* U1, const void* V1, const void* W1, double frac, void* u, void* v,
                     void* w, hipStream_t s) {
-  const int TI = kFuseCols / c->mx;
+  int TI = kFuseCols / c->mx;
   int TJ = 0;
-  if (TI >= 1 && c->mz <= kFuseMaxMz && !c->wx && !c->wy) {
+  // a walled axis needs every tile (the last one included) to hold at least
+  // two cells along it, so that the one-sided stencils stay inside the halo
+  while (c->wx && TI >= 2 && c->ncx % TI == 1) --TI;
+  if (TI >= 1 && c->mz <= kFuseMaxMz && !(c->wx && TI < 2)) {
     // rows per tile: every stage-z item (one per halo column and row) on its own lane
     TJ = std::min(std::min(MR_FUSED_ROWS, 256 / (TI + 3) - 2), c->ncy);
     while (TJ >= 1 && fused_lds<T>(TI, TJ, c->mx, c->my, c->mz) > kFuseMaxLds) --TJ;
+    if (c->wy) {
+      while (TJ >= 2 && c->ncy % TJ == 1) --TJ;
+      if (TJ < 2) TJ = 0;
+    }
   }
   if (MR_FUSED_REFINE && TJ >= 1) {
     RefArgs<T> a = ref_args<T>(c, g);

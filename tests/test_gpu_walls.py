@@ -116,6 +116,23 @@ def test_refine_parity_with_walls(walls, prec):
         assert np.all(got[1][:, 0] == 0)
 
 
+@pytest.mark.parametrize("nc,m", [((33, 9, 4), (2, 2, 2)), ((3, 3, 3), (3, 3, 2)), ((65, 13, 3), (1, 3, 4))])
+def test_refine_parity_with_walls_tile_edges(nc, m):
+    """Walled sizes whose last refinement tile would hold a single coarse cell
+    (33 columns in tiles of 32, 9 and 13 rows in tiles of 4): the launcher
+    narrows the tiles so that the one-sided wall stencils stay in the halo."""
+    print("case walls refine tile edges", nc, m, flush=True)
+    c = WallCase(nc, m, (True, True))
+    U, V, W = c.coarse_velocity()
+    want = O.refine_velocity(c.g, U, V, W)
+    Ul, Vl = c.to_lib(U, V)
+    with c.ctx() as ctx:
+        got = [host(t) for t in ctx.interpolate_velocity(c.d(Ul), c.d(Vl), c.d(W))]
+    gu, gv = c.to_oracle(got[0], got[1])
+    for a, b in zip((gu, gv, got[2]), want):
+        assert rel_max(a, b) <= FP64_TOL
+
+
 def _stream_field(c):
     """Coarse velocity of psi(x, z) = sin(pi x) sin(pi z) (no flow through the
     x walls or the plates; divergence-free by Stokes), oracle layout."""
