@@ -10,7 +10,8 @@ Also reported, outside the timed region: the same workload with FP32 storage,
 the adjoint workload (FP32, 20 steps, checkpoint every 5: forward and backward
 times), the inter-grid kernels (integration, Nu_T, refinement in time, one
 coarse step of M_t = 4), the step and refinement with side walls in x and y,
-the FP32 step kernel on the 576^3 and
+the step with an explicit z-diffusion share of 1/2 and with fourth-order face
+values, the FP32 step kernel on the 576^3 and
 1024x1024x512 workloads, the copy-kernel bandwidth, the roofline of the
 dominant kernel (the fused scalar step) and the oracle's CPU time on a
 bounded sample.
@@ -437,7 +438,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_kernel_ms": ms_step,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     # measured HBM bytes (committed counters) over the live kernel time
+                     "traffic_frac": (traffic / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None},
         "cpu_baseline": cpu,
     }
     line.update(extras)
