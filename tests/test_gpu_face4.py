@@ -75,6 +75,16 @@ def test_step_parity_face4_small_and_large(nc, m):
     _steps(c, 3, FP64_TOL)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc", [(1, 1, 1), (4, 1, 3), (2, 5, 2)])
+def test_step_parity_face4_single_cells_and_rows(nc, prec):
+    """A single cell (every stencil cell is itself), a single y row and two-cell
+    x, in both patch shapes (FP64 two-row patches, FP32 one-row)."""
+    print("case face4 tiny", nc, prec, flush=True)
+    c = Case4(nc, (1, 1, 1), PERIODIC, precision=prec, n_avg=2, gamma=0.0)
+    _steps(c, 3, FP64_TOL if prec == "fp64" else FP32_TOL)
+
+
 @pytest.mark.parametrize("walls", SIDES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_step_parity_face4_with_walls(walls, prec):
