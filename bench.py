@@ -156,22 +156,41 @@ def copy_bandwidth():
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
-def adjoint_times(steps_override=None):
+def adjoint_alg_values(w, N, K):
+    """Algorithmic values moved per dense cell by the forward and the backward
+    pass of a checkpointed rollout (N steps, checkpoint every K):
+    forward  = refinement 3(1 + 1/M^3) + 6 per step + 4 per stored pair
+               (read and write of two fields every K steps, except at step 0: one)
+               + 2 for the returned copy;
+    backward = loss gradient 3 + seed 2 + per segment: recompute (len-1) x 6,
+               reverse steps len x 6, velocity gradient 2 len + 6; + transposed
+               refinement 3(1 + 1/M^3) + 3 zeroed gradients."""
+    mcube = w.m[0] * w.m[1] * w.m[2]
+    ref = 3.0 * (1.0 + 1.0 / mcube)
+    segs = [min(s + K, N) - s for s in range(0, N, K)]
+    fwd = ref + 6.0 * N + 4.0 * (len(segs) - 1) + 2.0 + 2.0
+    bwd = 3.0 + 2.0 + sum(6.0 * (L - 1) + 6.0 * L + 2.0 * L + 6.0 for L in segs) + ref + 3.0
+    return fwd, bwd
+
+
+def adjoint_times(wname=ADJOINT_WORKLOAD, reps=3):
     """Forward (refine + N steps) and backward (recompute + reverse steps +
-    velocity gradient + transposed refinement) of the adjoint workload."""
+    velocity gradient + transposed refinement) of an adjoint workload (FP32):
+    median times, cell-step throughput and % of HBM peak of each pass."""
     from paper_1805_03426_amd.autograd import rollout
-    w = WORKLOADS[ADJOINT_WORKLOAD]
+    w = WORKLOADS[wname]
     r = Run(w, "fp32")
-    N = steps_override or w.steps
+    N, K = w.steps, w.ckpt_every
     th0 = r.th0.clone().requires_grad_(True)
     U, V, W = (t.clone().requires_grad_(True) for t in (r.U, r.V, r.W))
     target = torch.from_numpy(inputs.theta_initial(r.host_inputs["zf"], r.ctx.nx, r.ctx.ny,
                                                    seed=inputs.SEED_TARGET)).to("cuda", torch.float32)
+    del r.ring, r.runner, r.u, r.v, r.w_   # the rollout refines and steps on its own buffers
     tf, tb = [], []
-    for rep in range(3):
+    for rep in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = rollout(r.ctx, th0, U, V, W, N, w.ckpt_every)
+        out = rollout(r.ctx, th0, U, V, W, N, K)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         g = out - target
@@ -182,8 +201,16 @@ def adjoint_times(steps_override=None):
             tf.append(t1 - t0)
             tb.append(t2 - t1)
         th0.grad = U.grad = V.grad = W.grad = None
+        del out, g
     r.ctx.close()
-    return float(np.median(tf)), float(np.median(tb)), N
+    tf, tb = float(np.median(tf)), float(np.median(tb))
+    vf, vb = adjoint_alg_values(w, N, K)
+    frac = lambda values, t: values * 4 * w.cells / t / 1e9 / HBM_PEAK_GBS
+    return dict(workload=wname, steps=N, ckpt_every=K, forward_s=tf, backward_s=tb,
+                backward_over_forward=tb / tf,
+                forward_cell_steps_per_s=w.cells * N / tf, backward_cell_steps_per_s=w.cells * N / tb,
+                forward_hbm_frac_alg=frac(vf, tf), backward_hbm_frac_alg=frac(vb, tb),
+                alg_values_per_cell=dict(forward=vf, backward=vb))
 
 
 def _event_ms(fn, reps=20, warmup=3):
@@ -386,9 +413,7 @@ def main():
         del r32
         torch.cuda.empty_cache()
         print("bench: adjoint", file=sys.stderr, flush=True)
-        tf, tb, nad = adjoint_times()
-        extras["adjoint"] = dict(workload=ADJOINT_WORKLOAD, steps=nad, forward_s=tf, backward_s=tb,
-                                 backward_over_forward=tb / tf)
+        extras["adjoint"] = adjoint_times()
         torch.cuda.empty_cache()
         print("bench: inter-grid kernels", file=sys.stderr, flush=True)
         extras["intergrid"] = intergrid_times(w)
@@ -404,6 +429,10 @@ def main():
         torch.cuda.empty_cache()
         print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
         extras["fp32_large"] = large_fp32_step_times()
+        torch.cuda.empty_cache()
+        print("bench: adjoint at 1024x1024x512", file=sys.stderr, flush=True)
+        extras["adjoint_large"] = adjoint_times("rb1024x1024x512-m2-fp32", reps=2)
+        torch.cuda.empty_cache()
         extras["copy_bandwidth_GBs"] = copy_bandwidth()
 
     if args.copy_probe:
