@@ -268,13 +268,14 @@ def intergrid_times(w, mt=4):
     return out
 
 
-def large_fp32_step_times():
-    """FP32 scalar-step kernel on the 576^3 (M = 3) and 1024x1024x512 workloads:
-    mean kernel time over a few steps and % of HBM peak (24 B per dense cell)."""
+def large_step_times():
+    """Scalar-step kernel on the 576^3 (M = 3) workload in FP32 and in FP64 (the
+    precision tier's reference run) and on 1024x1024x512 in FP32: mean kernel
+    time over a few steps and % of HBM peak (6 values per dense cell)."""
     out = {}
-    for name in ("rb576-m3-fp32", "rb1024x1024x512-m2-fp32"):
+    for name, prec in (("rb576-m3-fp32", "fp32"), ("rb576-m3-fp32", "fp64"), ("rb1024x1024x512-m2-fp32", "fp32")):
         w = WORKLOADS[name]
-        r = Run(w, "fp32")
+        r = Run(w, prec)
         c = r.ctx
         c.interpolate_velocity(r.U, r.V, r.W, out=(r.u, r.v, r.w_))
         state = {"n": 0, "prev": 0, "cur": 0}
@@ -285,8 +286,10 @@ def large_fp32_step_times():
             state.update(n=n + 1, prev=state["cur"], cur=out)
 
         ms = _event_ms(step, reps=10, warmup=2)
-        out[name] = dict(step_kernel_ms=ms, dense_cell_updates_per_s=w.cells / (ms * 1e-3),
-                         step_hbm_frac_alg=24 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        nbytes = 6 * (8 if prec == "fp64" else 4) * w.cells
+        key = name if prec == "fp32" else name.replace("fp32", "fp64")
+        out[key] = dict(step_kernel_ms=ms, dense_cell_updates_per_s=w.cells / (ms * 1e-3),
+                        step_hbm_frac_alg=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         c.close()
         del r
         torch.cuda.empty_cache()
@@ -427,8 +430,8 @@ def main():
         print("bench: step with fourth-order faces", file=sys.stderr, flush=True)
         extras["face_order4"] = variant_step_times(w, face_order=4)
         torch.cuda.empty_cache()
-        print("bench: FP32 step at 576^3 and 1024x1024x512", file=sys.stderr, flush=True)
-        extras["fp32_large"] = large_fp32_step_times()
+        print("bench: step at 576^3 (FP32, FP64) and 1024x1024x512 (FP32)", file=sys.stderr, flush=True)
+        extras["large_steps"] = large_step_times()
         torch.cuda.empty_cache()
         print("bench: adjoint at 1024x1024x512", file=sys.stderr, flush=True)
         extras["adjoint_large"] = adjoint_times("rb1024x1024x512-m2-fp32", reps=2)
