@@ -621,6 +621,7 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
     MR_CASE(16)
     MR_CASE(24)
     MR_CASE(32)
+    MR_CASE(36)
     MR_CASE(40)
 #undef MR_CASE
     default:

@@ -183,11 +183,13 @@ def test_step_parity_averaging_and_adiabatic():
 
 @pytest.mark.parametrize("nc,m,gamma", [((5, 3, 7), (3, 1, 2), 1.0), ((4, 4, 1), (2, 2, 1), 0.0),
                                         ((3, 3, 160), (5, 1, 4), 2.5), ((33, 3, 3), (3, 2, 3), 1.0),
-                                        ((1, 1, 1), (1, 1, 1), 0.0), ((1, 2, 2), (1, 1, 1), 0.5)])
+                                        ((1, 1, 1), (1, 1, 1), 0.0), ((1, 2, 2), (1, 1, 1), 0.5),
+                                        ((3, 3, 275), (4, 1, 2), 2.0)])
 def test_step_parity_ragged(nc, m, gamma):
     """x not a multiple of 64, a single z level, the largest z (640 levels:
-    16 chunks of 40), a ragged last chunk, stretched x, a single cell (its own
-    periodic neighbour on every side) and single-column grids."""
+    16 chunks of 40), 550 levels (16 chunks of 36, the last one ragged), a
+    ragged last chunk, stretched x, a single cell (its own periodic neighbour
+    on every side) and single-column grids."""
     print("case step ragged", nc, m, flush=True)
     case = Case(nc, m, gamma, kmax=1, stretch_x=True, n_avg=2, random_velocity=True)
     _step_parity(case, 4, FP64_TOL)
