@@ -7,8 +7,9 @@
 namespace mr {
 namespace line {
 // The forward and reverse variants of the line kernel are instantiated in
-// k_line_fwd.hip, k_line_bwd.hip and k_line_bwd0.hip (one translation unit
-// each, so that they compile in parallel); the seed solve here.
+// k_line_fwd.hip, k_line_bwd64.hip, k_line_bwd32.hip and k_line_bwd0.hip
+// (translation units of their own, so that they compile in parallel); the
+// seed solve here.
 extern template hipError_t launch_line<double, FWD>(mr_ctx*, LineArgs<double>, hipStream_t);
 extern template hipError_t launch_line<float, FWD>(mr_ctx*, LineArgs<float>, hipStream_t);
 extern template hipError_t launch_line<double, BWD>(mr_ctx*, LineArgs<double>, hipStream_t);
