@@ -89,7 +89,14 @@ def _stream():
 
 
 class Context:
-    """Grid tables on the current GPU plus typed entry points."""
+    """Grid tables on the current GPU plus typed entry points.
+
+    Arguments as for ``make_desc``: dense face coordinates xf, yf, zf,
+    refinement factors m = (mx, my, mz), Ra, Pr, the fixed time step dt, the
+    averaging period n_avg (Eq. 7), the wall conditions and values of the
+    scalar, the storage precision ("fp64" or "fp32"), the x and y sides
+    ("periodic" or "walls"), the explicit share z_explicit of the z diffusion
+    (0 to 1/2) and the face order of the advection (2 or 4)."""
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
                  bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
