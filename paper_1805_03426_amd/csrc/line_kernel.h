@@ -617,9 +617,6 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   case LL:                                                                                      \
     launch_variant<T, LL, MODE, rows, mb, pf>(walls, expz, ord4, grid, block, s, a);            \
     break;
-    MR_CASE(8)
-    MR_CASE(16)
-    MR_CASE(24)
     MR_CASE(32)
     MR_CASE(36)
     MR_CASE(40)

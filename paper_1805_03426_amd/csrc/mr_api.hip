@@ -310,7 +310,7 @@ bool z_factors(int nz, int L, const double* sub, const double* diag, const doubl
 #define MR_MIN_L64 32
 #endif
 #ifndef MR_MIN_L32
-#define MR_MIN_L32 8
+#define MR_MIN_L32 32
 #endif
 int choose_chunks(int nz, int precision, int& L, int& nch) {
   const int min_len = precision == MR_FP64 ? MR_MIN_L64 : MR_MIN_L32;

@@ -16,7 +16,7 @@ enum StepKind { KIND_STARTUP = 0, KIND_LEAPFROG = 1, KIND_AVERAGE = 2, NKINDS = 
 // Largest number of z chunks (one wavefront each) of the line solver, and the
 // chunk lengths the step kernels are instantiated for.
 constexpr int kMaxChunks = 16;
-constexpr int kChunkLens[] = {8, 16, 24, 32, 36, 40};
+constexpr int kChunkLens[] = {32, 36, 40};
 constexpr int kWave = 64;
 
 // Grid tables of one precision (device pointers into the context's table block).
