@@ -201,3 +201,13 @@ def test_null_arguments_rejected():
     assert L.mr_scalar_step(None, 0, None, None, None, None, None, None, None) == _lib.MR_EINVAL
     assert L.mr_nusselt(None, None, None, None, None, None) == _lib.MR_EINVAL
     assert L.mr_copy_probe(None, None, 16, None) == _lib.MR_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; more than one exits with a message before any GPU work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
