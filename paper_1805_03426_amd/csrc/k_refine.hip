@@ -640,6 +640,9 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
 #ifndef MR_FUSED_WGS
 #define MR_FUSED_WGS 8192
 #endif
+#ifndef MR_FUSED_MIN_KC
+#define MR_FUSED_MIN_KC 4
+#endif
 constexpr size_t kFuseMaxLds = 64 * 1024;
 
 // LDS bytes of refine_fused for a tile of TI x TJ coarse cells.
@@ -675,7 +678,10 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
     const int nbx = (c->ncx + TI - 1) / TI, nby = (c->ncy + TJ - 1) / TJ;
     const int64_t tiles = (int64_t)nbx * nby;
     // coarse layers per workgroup: enough workgroups to fill the chip
+    // (at least MR_FUSED_MIN_KC layers each, so that the table set-up and the first
+    // layer's loads are shared by a few layers)
     int nkc = (int)std::max<int64_t>(1, std::min<int64_t>(c->ncz, (MR_FUSED_WGS + tiles - 1) / tiles));
+    nkc = std::min(nkc, std::max(1, c->ncz / MR_FUSED_MIN_KC));
     const int KC = (c->ncz + nkc - 1) / nkc;
     nkc = (c->ncz + KC - 1) / KC;
     const int64_t nb = tiles * nkc;
