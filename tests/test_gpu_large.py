@@ -113,8 +113,90 @@ def test_rb576_sampled_and_fp32_drift():
         assert max(nu_err.values()) < 1e-3
 
 
+def _separable(seed, nx, ny, nz, terms=2):
+    """Factors of a seeded field f(k, j, i) = b_k + sum_t a_tk cy_tj cx_ti:
+    O(1) values with grid-scale variation in x and y (which the transposed
+    stencils see), cheap to build level by level or on a window."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(nz), [tuple(rng.standard_normal(n) for n in (nz, ny, nx)) for _ in range(terms)]
+
+
+def _sep_eval(f, ks, js, is_):
+    """The field at levels ks, rows js, columns is_, rounded to FP32 as the GPU holds it."""
+    b, terms = f
+    out = np.broadcast_to(b[ks][:, None, None], (len(ks), len(js), len(is_)))
+    for a, cy, cx in terms:
+        out = out + a[ks][:, None, None] * (cy[js][None, :, None] * cx[is_][None, None, :])
+    return out.astype(np.float32).astype(np.float64)
+
+
+def _sep_device(f, ctx):
+    nz, ny, nx = ctx.shape_cell
+    t = ctx.empty(ctx.shape_cell)
+    js, is_ = np.arange(ny), np.arange(nx)
+    for k in range(nz):
+        t[k].copy_(torch.from_numpy(_sep_eval(f, np.array([k]), js, is_)[0].astype(np.float32)))
+    return t
+
+
+def _sampled_backward_checks(w, d, ctx, cols, uvw, tol):
+    """The reverse pass of the FP32 context on sampled columns against the
+    windowed oracle: the seed, the fused reverse step of every kind (start-up,
+    leapfrog, before an averaging step, the last step with no later one) and
+    the deferred velocity gradient of two steps, from seeded separable mu and
+    theta fields.  Returns the largest relative L2 error."""
+    nx, ny, nz = w.n
+    mx, my, _ = w.m
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    gz = O.Grid(np.arange(4) / nx, np.arange(4) / ny, d["zf"], (1, 1, 1))
+    fa, fb, ft = (_separable(s, nx, ny, nz) for s in (31, 32, 33))
+    mu_a, mu_b, th = (_sep_device(f, ctx) for f in (fa, fb, ft))
+    windows = {c: S.refine_window(d["U"], d["V"], d["W"], w.m, d["zf"], nx, ny, c[0] // mx, c[1] // my)
+               for c in cols}
+
+    def win(f, i, j):
+        return _sep_eval(f, np.arange(nz), np.arange(j - 1, j + 2) % ny, np.arange(i - 1, i + 2) % nx)
+
+    def gather(t):
+        torch.cuda.synchronize()
+        return np.stack([t[:, j, i].double().cpu().numpy() for (i, j) in cols])
+
+    worst = 0.0
+    out = ctx.empty(ctx.shape_cell)
+    last = w.steps - 1
+    ctx.adjoint_seed(last, mu_a, out)
+    want = np.stack([S.seed(gz, p, last, win(fa, i, j)[:, 1, 1]) for (i, j) in cols])
+    worst = max(worst, _rel_l2(gather(out), want))
+    assert worst <= tol, ("seed", worst)
+    cases = [(0, True), (1, True), (w.n_avg - 2, True), (last, False)]
+    for n, has_next in cases:
+        ctx.scalar_step_backward(n, mu_a if has_next else None, mu_b, None, out, *uvw)
+        want = np.stack([S.backward_column(win(fa, i, j) if has_next else None, win(fb, i, j), win(ft, i, j),
+                                           *windows[(i, j)], d["zf"], nx, ny, p, n, i, j)[0] for (i, j) in cols])
+        e = _rel_l2(gather(out), want)
+        worst = max(worst, e)
+        assert e <= tol, (n, e)
+    del out
+    gu, gv, gw = torch.zeros_like(uvw[0]), torch.zeros_like(uvw[1]), torch.zeros_like(uvw[2])
+    steps = [(1, fb), (w.n_avg - 1, fa)]
+    ctx.velocity_grad([n for n, _ in steps], [th, th], [mu_b if f is fb else mu_a for _, f in steps], gu, gv, gw)
+    wants = [[np.zeros(nz), np.zeros(nz), np.zeros(nz + 1)] for _ in cols]
+    for n, f in steps:
+        for c, (i, j) in enumerate(cols):
+            grads = S.backward_column(None, win(f, i, j), win(ft, i, j), *windows[(i, j)], d["zf"], nx, ny, p, n,
+                                      i, j)[1]
+            for acc, g in zip(wants[c], grads):
+                acc += g
+    for q, t in enumerate((gu, gv, gw)):
+        e = _rel_l2(gather(t), np.stack([wc[q] for wc in wants]))
+        worst = max(worst, e)
+        assert e <= tol, ("velocity gradient", q, e)
+    return worst
+
+
 def test_rb1024_fp32_sampled():
-    """1024x1024x512 FP32: refinement and steps on sampled columns."""
+    """1024x1024x512 FP32: refinement, forward steps and the reverse pass
+    (seed, reverse steps, velocity gradient) on sampled columns."""
     print("case rb1024x1024x512 fp32 full size", flush=True)
     w = WORKLOADS["rb1024x1024x512-m2-fp32"]
     d = inputs.workload_inputs(w)
@@ -122,9 +204,11 @@ def test_rb1024_fp32_sampled():
     cols = S.sample_columns(nx, ny, w.m[0], w.m[1], 5, seed=12)
     th0 = d["theta0"]
     with _ctx(d, w, "fp32") as c32:
-        r, s, _ = _sampled_checks(w, d, c32, torch.float32, 1e-5, 1e-5, cols, th0,
-                                  [(0, th0), (1, th0), (49, th0)])
-    print("rb1024x1024x512 sampled: refine %.2e step %.2e" % (r, s), flush=True)
+        r, s, uvw = _sampled_checks(w, d, c32, torch.float32, 1e-5, 1e-5, cols, th0,
+                                    [(0, th0), (1, th0), (49, th0)])
+        print("rb1024x1024x512 sampled: refine %.2e step %.2e" % (r, s), flush=True)
+        b = _sampled_backward_checks(w, d, c32, cols, uvw, 1e-5)
+    print("rb1024x1024x512 sampled reverse pass: %.2e" % b, flush=True)
 
 
 def _fp64_loss(c64, d, th0, U, V, W, N, target):
