@@ -114,7 +114,11 @@ typedef struct {
  * refinement factor < 1, fewer than 3 coarse cells on an axis with factor > 1,
  * non-increasing faces, dt <= 0, Ra*Pr <= 0, an unknown wall condition or
  * precision, or an explicit x/y diffusion number
- * 2 dt kappa (4/hx_min^2 + 4/hy_min^2) above 1.  *out is set only on success. */
+ * 2 dt kappa (4/hx_min^2 + 4/hy_min^2) above 1.  Fails with MR_ESHAPE on sizes
+ * the kernels cannot address: an axis of more than 2^20 dense cells,
+ * (N_z + 1) N_x N_y above 2^31 - 1 values, one z level (N_x N_y values of the
+ * context's precision) above 2^32 - 1 bytes, or more than 640 z levels (the
+ * line solver's 16 chunks of at most 40 levels).  *out is set only on success. */
 int mr_init(const mr_desc* desc, mr_ctx** out);
 
 /* Free the context and its device tables.  NULL is accepted. */

@@ -206,6 +206,8 @@ int check_desc(const mr_desc* d, Problem& P) {
   if (d->bc_bot != MR_DIRICHLET && d->bc_bot != MR_ADIABATIC) return MR_EINVAL;
   if (d->bc_top != MR_DIRICHLET && d->bc_top != MR_ADIABATIC) return MR_EINVAL;
   if (d->precision != MR_FP64 && d->precision != MR_FP32) return MR_EINVAL;
+  // the step kernels address a z level with 32-bit byte offsets
+  if (nx * ny * (d->precision == MR_FP64 ? 8 : 4) > (int64_t)UINT32_MAX) return MR_ESHAPE;
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return MR_EINVAL;
   if (!(d->ra > 0.0) || !(d->pr > 0.0) || !std::isfinite(d->ra * d->pr)) return MR_EINVAL;
   if (d->n_avg < 0) return MR_EINVAL;

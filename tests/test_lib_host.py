@@ -211,3 +211,17 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_init_rejects_levels_beyond_32bit_byte_offsets():
+    """A z level of 24000 x 24000 cells holds 5.76e8 values: 2.3 GB in FP32 is
+    addressable with the step's 32-bit byte offsets, 4.6 GB in FP64 is not
+    (MR_ESHAPE), although (nz + 1) nx ny stays below 2^31 with one level."""
+    f = inputs.uniform_faces(24000)
+    zf = inputs.uniform_faces(1)
+    d32, keep32 = make_desc(f, f, zf, (1, 1, 1), ra=1.0, pr=1.0, dt=1e-12, precision="fp32")
+    host_z_system(d32, 0)
+    d64, keep64 = make_desc(f, f, zf, (1, 1, 1), ra=1.0, pr=1.0, dt=1e-12, precision="fp64")
+    with pytest.raises(_lib.MRError) as e:
+        host_z_system(d64, 0)
+    assert e.value.status == _lib.MR_ESHAPE
