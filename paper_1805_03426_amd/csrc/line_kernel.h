@@ -49,6 +49,8 @@ struct LineArgs {
   int nx, ny, nz, nch;
   int band;            // x tiles per band of the tile walk (see line_kernel)
   int wx, wy;          // x / y bounded by adiabatic no-slip walls (else periodic)
+  T uhx, uhy;          // UXY kernels: 1/h of the uniform x and y widths
+  T uxx, uyy;          // UXY kernels: 1/h^2 of x and y
 };
 
 // Values one z level of the stencil reads.
@@ -162,10 +164,12 @@ __device__ __forceinline__ double lane_shl(double v) {
 // load (two rows per patch: the other row's halo value by a cross-lane
 // shuffle); the z pair from carrying one more level.  The reverse step's
 // transposed faces also need u, v, w on the faces one beyond each side.
-template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS, bool EXPZ, bool ORD4>
+template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS, bool EXPZ, bool ORD4,
+          bool UXY = false>
 __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   static_assert(!((EXPZ || ORD4) && MODE == SEED), "the seed solve has no stencil");
   static_assert(!ORD4 || (ROWS <= 2 && MR_XDPP), "fourth-order faces need patches of at most two rows");
+  static_assert(!UXY || !(WALLS || EXPZ || ORD4), "uniform-width kernels exist for the plain variant only");
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
   const int lane = threadIdx.x;
@@ -235,10 +239,12 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   const bool zum = wx && i <= 1, zup2 = wx && i + 2 >= nx;
   const bool zvm = wy && j <= 1, zvp2 = wy && j + 2 >= ny;
 
-  const T ihx = g.ihx[i], ihxm = g.ihx[im], ihxp = g.ihx[ip];
-  const T idx0 = g.idxc[i], idx1 = g.idxc[ip];
-  const T ihy = g.ihy[j], ihym = g.ihy[jm], ihyp = g.ihy[jp];
-  const T idy0 = g.idyc[j], idy1 = g.idyc[jp];
+  // UXY (uniform x and y widths, periodic): every width and centre distance
+  // of an axis is one wave-uniform kernel argument, so no lane holds them
+  const T ihx = UXY ? A.uhx : g.ihx[i], ihxm = UXY ? A.uhx : g.ihx[im], ihxp = UXY ? A.uhx : g.ihx[ip];
+  const T idx0 = UXY ? A.uhx : g.idxc[i], idx1 = UXY ? A.uhx : g.idxc[ip];
+  const T ihy = UXY ? A.uhy : g.ihy[j], ihym = UXY ? A.uhy : g.ihy[jm], ihyp = UXY ? A.uhy : g.ihy[jp];
+  const T idy0 = UXY ? A.uhy : g.idyc[j], idy1 = UXY ? A.uhy : g.idyc[jp];
   const T half = T(0.5);
   T ihxm2 = T(0), ihxp2 = T(0), ihym2 = T(0), ihyp2 = T(0);
   if constexpr (ORD4 && MODE != FWD) {
@@ -436,8 +442,9 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
                          (cur.v1 * (zc + cur.yp) - cur.v0 * (cur.ym + zc)) * ihy + (fzr - fzl) * ihz);
         }
         // lagged x/y diffusion of theta^{n-1}
-        const T lap = ((cur.pxp - cur.pc) * idx1 - (cur.pc - cur.pxm) * idx0) * ihx +
-                      ((cur.pyp - cur.pc) * idy1 - (cur.pc - cur.pym) * idy0) * ihy;
+        const T lap = UXY ? (cur.pxp + cur.pxm - T(2) * cur.pc) * A.uxx + (cur.pyp + cur.pym - T(2) * cur.pc) * A.uyy
+                          : ((cur.pxp - cur.pc) * idx1 - (cur.pc - cur.pxm) * idx0) * ihx +
+                                ((cur.pyp - cur.pc) * idy1 - (cur.pc - cur.pym) * idy0) * ihy;
         r = A.ap * cur.pc + A.ac * zc + A.tau * adv + A.tk * lap;
         if constexpr (EXPZ)   // explicit share of the z diffusion of the lagged level
           r += A.tkw * (g.lzd[k] * cur.pc + g.lzl[k] * pzm + g.lzh[k] * cur.pzp);
@@ -469,13 +476,15 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
         }
         // contribution of step n+1 through theta^n as its lagged level
         const T qx = cur.pc * ihx, qy = cur.pc * ihy;
-        const T lt = ((cur.pxm * ihxm - qx) * idx0 - (qx - cur.pxp * ihxp) * idx1) +
-                     ((cur.pym * ihym - qy) * idy0 - (qy - cur.pyp * ihyp) * idy1);
+        const T lt = UXY ? (cur.pxp + cur.pxm - T(2) * cur.pc) * A.uxx + (cur.pyp + cur.pym - T(2) * cur.pc) * A.uyy
+                         : ((cur.pxm * ihxm - qx) * idx0 - (qx - cur.pxp * ihxp) * idx1) +
+                               ((cur.pym * ihym - qy) * idy0 - (qy - cur.pyp * ihyp) * idy1);
         r = A.ac * zc + A.tau * cu + A.ap1 * cur.pc + A.tk1 * lt + A.s2 * cur.q;
         if (MODE == BWD0) {
           // the start-up step also reads theta^0 for its diffusion
-          const T l0 = ((cur.xm * ihxm - qc_x) * idx0 - (qc_x - cur.xp * ihxp) * idx1) +
-                       ((cur.ym * ihym - qc_y) * idy0 - (qc_y - cur.yp * ihyp) * idy1);
+          const T l0 = UXY ? (cur.xp + cur.xm - T(2) * zc) * A.uxx + (cur.yp + cur.ym - T(2) * zc) * A.uyy
+                           : ((cur.xm * ihxm - qc_x) * idx0 - (qc_x - cur.xp * ihxp) * idx1) +
+                                 ((cur.ym * ihym - qc_y) * idy0 - (qc_y - cur.yp * ihyp) * idy1);
           r += A.tk * l0;
           if constexpr (EXPZ) r += A.tkw * (g.lzd[k] * zc + g.lztl[k] * zm + g.lzth[k] * zp);
         }
@@ -571,11 +580,12 @@ struct StepLayout {
   static constexpr int prefetch = sizeof(T) == 8 ? MR_PFD64 : MR_PFD32;  // levels whose loads run ahead of the arithmetic
 };
 
-// Compile-time variants: side walls, explicit z share, fourth-order faces
-// (the seed solve has no stencil: one variant).
-template <typename T, int LL, int MODE, int R, int MB, int PF, bool W, bool E, bool O>
+// Compile-time variants: side walls, explicit z share, fourth-order faces,
+// and for the plain periodic variant uniform x and y widths (the seed solve
+// has no stencil: one variant).
+template <typename T, int LL, int MODE, int R, int MB, int PF, bool W, bool E, bool O, bool U = false>
 void launch_one(dim3 grid, dim3 block, hipStream_t s, const LineArgs<T>& a) {
-  hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, W, E, O>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, W, E, O, U>), grid, block, 0, s, a);
 }
 
 template <typename T, int LL, int MODE, int R, int MB, int PF, bool W>
@@ -590,12 +600,13 @@ void launch_eo(bool expz, bool ord4, dim3 grid, dim3 block, hipStream_t s, const
 }
 
 template <typename T, int LL, int MODE, int R, int MB, int PF>
-void launch_variant(bool walls, bool expz, bool ord4, dim3 grid, dim3 block, hipStream_t s,
+void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 block, hipStream_t s,
                     const LineArgs<T>& a) {
   if constexpr (MODE == SEED) {
     launch_one<T, LL, MODE, R, MB, PF, false, false, false>(grid, block, s, a);
   } else {
     if (walls) launch_eo<T, LL, MODE, R, MB, PF, true>(expz, ord4, grid, block, s, a);
+    else if (uxy && !expz && !ord4) launch_one<T, LL, MODE, R, MB, PF, false, false, false, true>(grid, block, s, a);
     else launch_eo<T, LL, MODE, R, MB, PF, false>(expz, ord4, grid, block, s, a);
   }
 }
@@ -612,10 +623,15 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   const bool walls = a.wx || a.wy;
   const bool expz = MODE != SEED && c->z_explicit > 0.0;
   const bool ord4 = MODE != SEED && c->face_order == 4;
+  const bool uxy = c->uniform_xy != 0;
+  a.uhx = (T)c->uhx;
+  a.uhy = (T)c->uhy;
+  a.uxx = (T)(c->uhx * c->uhx);
+  a.uyy = (T)(c->uhy * c->uhy);
   switch (c->L) {
 #define MR_CASE(LL)                                                                             \
   case LL:                                                                                      \
-    launch_variant<T, LL, MODE, rows, mb, pf>(walls, expz, ord4, grid, block, s, a);            \
+    launch_variant<T, LL, MODE, rows, mb, pf>(walls, expz, ord4, uxy, grid, block, s, a);       \
     break;
     MR_CASE(32)
     MR_CASE(36)

@@ -592,6 +592,9 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   c->wy = desc->side_y == MR_WALLS;
   c->z_explicit = desc->z_explicit;
   c->face_order = desc->face_order == 4 ? 4 : 2;
+  c->uniform_xy = !c->wx && !c->wy && uniform_axis(P.x) && uniform_axis(P.y);
+  c->uhx = P.x.n / (P.x.f[P.x.n] - P.x.f[0]);
+  c->uhy = P.y.n / (P.y.f[P.y.n] - P.y.f[0]);
   c->L = L; c->nch = nch;
   for (int k = 0; k < mr::NKINDS; ++k) c->tau[k] = taus[k];
   {

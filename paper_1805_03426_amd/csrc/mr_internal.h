@@ -79,6 +79,8 @@ struct mr_ctx {
   double kappa, dt, ra, pr, t_bot, t_top;
   int bc_bot, bc_top, n_avg;
   int wx, wy;                      // x / y bounded by adiabatic no-slip walls (else periodic)
+  int uniform_xy;                  // periodic x and y of equal widths (to 1e-13): uniform-width step kernels
+  double uhx, uhy;                 // 1/h of the x and y widths (used by those kernels)
   double z_explicit;               // w: share of the z diffusion explicit on the lagged level
   int face_order;                  // face value of the advected scalar: 2 or 4
   int device;

@@ -294,11 +294,12 @@ def _gpu_loss_grad(case, nsteps, target):
         return host(g0), host(gU), host(gV), host(gW)
 
 
-@pytest.mark.parametrize("nsteps,n_avg", [(6, 3), (18, 50)])
-def test_adjoint_parity(nsteps, n_avg):
-    """Reverse sweep on the GPU vs the oracle's discrete adjoint (FP64)."""
-    print("case adjoint", nsteps, n_avg, flush=True)
-    case = Case((8, 6, 7), (2, 3, 2), 1.5, ra=1e4, kmax=2, n_avg=n_avg)
+@pytest.mark.parametrize("nsteps,n_avg,stretch_x", [(6, 3, False), (18, 50, False), (6, 3, True)])
+def test_adjoint_parity(nsteps, n_avg, stretch_x):
+    """Reverse sweep on the GPU vs the oracle's discrete adjoint (FP64), on
+    uniform x and y (the uniform-width kernels) and on stretched x."""
+    print("case adjoint", nsteps, n_avg, stretch_x, flush=True)
+    case = Case((8, 6, 7), (2, 3, 2), 1.5, ra=1e4, kmax=2, n_avg=n_avg, stretch_x=stretch_x)
     target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
     _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, nsteps, target)
     g0, gU, gV, gW = _gpu_loss_grad(case, nsteps, target)
