@@ -635,7 +635,7 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
 #define MR_FUSED_REFINE 1
 #endif
 #ifndef MR_FUSED_ROWS
-#define MR_FUSED_ROWS 4
+#define MR_FUSED_ROWS 6
 #endif
 #ifndef MR_FUSED_WGS
 #define MR_FUSED_WGS 8192

@@ -116,11 +116,14 @@ def test_refine_parity_with_walls(walls, prec):
         assert np.all(got[1][:, 0] == 0)
 
 
-@pytest.mark.parametrize("nc,m", [((33, 9, 4), (2, 2, 2)), ((3, 3, 3), (3, 3, 2)), ((65, 13, 3), (1, 3, 4))])
+@pytest.mark.parametrize("nc,m", [((33, 9, 4), (2, 2, 2)), ((33, 11, 4), (2, 2, 2)), ((3, 3, 3), (3, 3, 2)),
+                                  ((65, 13, 3), (1, 3, 4)), ((22, 13, 3), (3, 2, 2))])
 def test_refine_parity_with_walls_tile_edges(nc, m):
     """Walled sizes whose last refinement tile would hold a single coarse cell
-    (33 columns in tiles of 32, 9 and 13 rows in tiles of 4): the launcher
-    narrows the tiles so that the one-sided wall stencils stay in the halo."""
+    (33 columns in tiles of 32, 11 rows in tiles of 5, 22 columns in tiles of
+    21, 13 rows in tiles of 6): the launcher narrows the tiles so that the
+    one-sided wall stencils stay in the halo.  65 x 13 with M_x = 1 takes the
+    three stage kernels (a one-row fused tile is too narrow for the walls)."""
     print("case walls refine tile edges", nc, m, flush=True)
     c = WallCase(nc, m, (True, True))
     U, V, W = c.coarse_velocity()
