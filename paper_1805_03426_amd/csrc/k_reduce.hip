@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kWave) max_final(const double* part, int n, do
 // the horizontal range p of faces kNuFaces*q .. kNuFaces*q + kNuFaces-1: each
 // lane walks those faces for its cells carrying theta of the level below, so a
 // level is read once per group of faces instead of once per face.
-constexpr int kNuFaces = 4;
+constexpr int kNuFaces = 2;   // timed: 2 faces per group beat 1, 3, 4, 8 and 16
 
 template <typename T>
 __global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const double* hx,
