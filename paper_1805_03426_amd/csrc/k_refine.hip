@@ -270,7 +270,7 @@ __host__ __device__ inline int fused_fields(int TI, int TJ, int my, int mz) {
          mz * TJ * (my + 1) * NXH;
 }
 
-template <typename T, bool BLEND>
+template <typename T, bool BLEND, bool NT>
 __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ, int nbx, int nby,
                                                     int KC) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -427,10 +427,22 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
       const T* R = tRx + 3 * col;
       const T a = rdot3(R, v0), c = rdot3(R, w0);
       const int o = k * nxy + j * nx + i;
-      A.out0[o] = uu;
-      A.out1[o] = a;
-      A.out2[o] = c;
-      if (k == nz - 1) A.out2[o + nxy] = rdot3(R, w1);
+      // NT: the dense faces are written once, so streaming stores keep L2 for
+      // the coarse halo; used when the tile's rows are whole 128-byte lines
+      // (partial lines stored that way were 37% slower at M_x = 3).  A compile-
+      // time flag: a runtime branch lets the compiler merge the two stores and
+      // drop the streaming hint.
+      if constexpr (NT) {
+        __builtin_nontemporal_store(uu, A.out0 + o);
+        __builtin_nontemporal_store(a, A.out1 + o);
+        __builtin_nontemporal_store(c, A.out2 + o);
+        if (k == nz - 1) __builtin_nontemporal_store(rdot3(R, w1), A.out2 + o + nxy);
+      } else {
+        A.out0[o] = uu;
+        A.out1[o] = a;
+        A.out2[o] = c;
+        if (k == nz - 1) A.out2[o + nxy] = rdot3(R, w1);
+      }
     }
     cur = nxt;
   }
@@ -687,10 +699,16 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
     const int64_t nb = tiles * nkc;
     if (nb > INT32_MAX) return hipErrorInvalidValue;
     const size_t lds = fused_lds<T>(TI, TJ, c->mx, c->my, c->mz);
-    if (U1)
-      hipLaunchKernelGGL((refine_fused<T, true>), dim3((unsigned)nb), dim3(256), lds, s, a, TI, TJ, nbx, nby, KC);
+    const bool nt = (TI * c->mx * sizeof(T)) % 128 == 0 && (c->nx * sizeof(T)) % 128 == 0;
+    const dim3 grid((unsigned)nb), block(256);
+    if (U1 && nt)
+      hipLaunchKernelGGL((refine_fused<T, true, true>), grid, block, lds, s, a, TI, TJ, nbx, nby, KC);
+    else if (U1)
+      hipLaunchKernelGGL((refine_fused<T, true, false>), grid, block, lds, s, a, TI, TJ, nbx, nby, KC);
+    else if (nt)
+      hipLaunchKernelGGL((refine_fused<T, false, true>), grid, block, lds, s, a, TI, TJ, nbx, nby, KC);
     else
-      hipLaunchKernelGGL((refine_fused<T, false>), dim3((unsigned)nb), dim3(256), lds, s, a, TI, TJ, nbx, nby, KC);
+      hipLaunchKernelGGL((refine_fused<T, false, false>), grid, block, lds, s, a, TI, TJ, nbx, nby, KC);
     return hipGetLastError();
   }
   const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
