@@ -159,17 +159,18 @@ def copy_bandwidth():
 def adjoint_alg_values(w, N, K):
     """Algorithmic values moved per dense cell by the forward and the backward
     pass of a checkpointed rollout (N steps, checkpoint every K):
-    forward  = refinement 3(1 + 1/M^3) + 6 per step + 4 per stored pair
-               (read and write of two fields every K steps, except at step 0: one)
-               + 2 for the returned copy;
-    backward = loss gradient 3 + seed 2 + per segment: recompute (len-1) x 6,
+    forward  = refinement 3(1 + 1/M^3) + 6 per step + 2 for the copy of theta^0
+               + 2 for the returned copy (the kept states are written in place);
+    backward = loss gradient 3 + seed 2 + per segment: recompute (len-1) x 6
+               (not for the last segment, whose states the forward kept),
                reverse steps len x 6, velocity gradient 2 len + 6; + transposed
                refinement 3(1 + 1/M^3) + 3 zeroed gradients."""
     mcube = w.m[0] * w.m[1] * w.m[2]
     ref = 3.0 * (1.0 + 1.0 / mcube)
     segs = [min(s + K, N) - s for s in range(0, N, K)]
-    fwd = ref + 6.0 * N + 4.0 * (len(segs) - 1) + 2.0 + 2.0
-    bwd = 3.0 + 2.0 + sum(6.0 * (L - 1) + 6.0 * L + 2.0 * L + 6.0 for L in segs) + ref + 3.0
+    fwd = ref + 6.0 * N + 2.0 + 2.0
+    recompute = sum(6.0 * (L - 1) for L in segs[:-1])
+    bwd = 3.0 + 2.0 + recompute + sum(6.0 * L + 2.0 * L + 6.0 for L in segs) + ref + 3.0
     return fwd, bwd
 
 

@@ -2,9 +2,11 @@
 
 ``ScalarRollout`` is a torch.autograd.Function whose forward refines the
 coarse velocity once (it is frozen over the rollout), runs N scalar steps on a
-ring of three buffers and keeps the pair (theta^{n-1}, theta^n) every K steps.
-Its backward walks the checkpoint segments in reverse: it recomputes the
-states of a segment from its checkpoint, runs the fused reverse step of each
+ring of three buffers and keeps the pair (theta^{n-1}, theta^n) every K steps
+and every state of the last segment; each kept state is written straight into
+a buffer of its own, so nothing is copied.  Its backward walks the checkpoint
+segments in reverse: it recomputes the states of each segment but the last
+from its checkpoint, runs the fused reverse step of each
 step (transposed implicit solve fused with the transposed stencils), adds the
 segment's dense face-velocity gradient once from the stored (theta^n, mu^n)
 pairs, and finally maps the dense face gradient to the coarse faces with the
@@ -23,21 +25,32 @@ class ScalarRollout(torch.autograd.Function):
             raise ValueError("nsteps must be >= 1")
         K = max(1, min(int(ckpt_every), MAX_GRAD_STEPS))
         u, v, w = mr.interpolate_velocity(U.detach(), V.detach(), W.detach())
-        ring = [theta0.detach(), mr.empty(mr.shape_cell), mr.empty(mr.shape_cell), mr.empty(mr.shape_cell)]
-        prev = cur = ring[0]
-        ckpts = {}
-        slot = 1
+        last = ((nsteps - 1) // K) * K          # first step of the last segment
+        th0 = theta0.detach().clone()
+        # theta^m that the backward reads (the checkpoint pairs (theta^{s-1},
+        # theta^s) and every state of the last segment) is written straight
+        # into a buffer of its own; the others rotate through three buffers
+        pool = [mr.empty(mr.shape_cell) for _ in range(3)]
+        prev = cur = th0
+        ckpts = {0: (None, th0)}
+        tail = {0: th0} if last == 0 else {}
         for n in range(nsteps):
-            if n % K == 0:
-                ckpts[n] = (None if n == 0 else prev.clone(), cur.clone())
-            out = ring[slot]
-            slot = 1 + (slot % 3)
+            m = n + 1
+            if m % K == 0 or (m + 1) % K == 0 or last <= m < nsteps:
+                out = mr.empty(mr.shape_cell)
+            else:
+                out = next(b for b in pool if b is not prev and b is not cur)
             mr.scalar_step(n, prev, cur, out, u, v, w)
             prev, cur = cur, out
+            if m < nsteps and m % K == 0:
+                ckpts[m] = (prev, cur)
+            if last <= m < nsteps:
+                tail[m] = cur
         fctx.mr = mr
         fctx.nsteps = nsteps
         fctx.K = K
         fctx.ckpts = ckpts
+        fctx.tail = tail
         fctx.uvw = (u, v, w)
         return cur.clone()
 
@@ -55,16 +68,21 @@ class ScalarRollout(torch.autograd.Function):
         g_theta0 = None
         for s in reversed(range(0, N, K)):
             e = min(s + K, N)
-            # recompute theta^s .. theta^{e-1}
-            pprev, pcur = fctx.ckpts[s]
-            states = {s: pcur}
-            prev = pprev if pprev is not None else pcur
-            cur = pcur
-            for n in range(s, e - 1):
-                out = mr.empty(mr.shape_cell)
-                mr.scalar_step(n, prev, cur, out, u, v, w)
-                states[n + 1] = out
-                prev, cur = cur, out
+            if s == (N - 1) // K * K:
+                # the last segment's states were kept by the forward pass
+                states = fctx.tail
+                fctx.tail = None
+            else:
+                # recompute theta^s .. theta^{e-1} from the checkpoint
+                pprev, pcur = fctx.ckpts[s]
+                states = {s: pcur}
+                prev = pprev if pprev is not None else pcur
+                cur = pcur
+                for n in range(s, e - 1):
+                    out = mr.empty(mr.shape_cell)
+                    mr.scalar_step(n, prev, cur, out, u, v, w)
+                    states[n + 1] = out
+                    prev, cur = cur, out
             # reverse steps e-1 .. s; mu^n is kept for the velocity gradient
             mus = {}
             for n in range(e - 1, s - 1, -1):
