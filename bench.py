@@ -90,22 +90,31 @@ class Run:
         self.prof = torch.empty((max(1, self.nprof), c.nz + 6), dtype=torch.float64, device="cuda")
         self.host_inputs = d
 
+    def step_groups(self):
+        """Ranges [n0, n1) of steps launched back to back (between two Nusselt calls)."""
+        w = self.w
+        g = w.nu_every if w.nu_every else w.steps
+        return [(n0, min(n0 + g, w.steps)) for n0 in range(0, w.steps, g)]
+
     def run(self, events=None):
         """One whole run; with ``events`` (a list of (start, end) event pairs,
-        one per step) it records a pair around every scalar-step launch on
-        the current stream."""
+        one per range of ``step_groups``) it records a pair on the current
+        stream around each range of back-to-back scalar-step launches."""
         c, w = self.ctx, self.w
         c.interpolate_velocity(self.U, self.V, self.W, out=(self.u, self.v, self.w_))
         c.divergence(self.u, self.v, self.w_, out=self.div)
         prev = cur = 0
         q = 0
+        groups = self.step_groups()
+        starts = {n0: i for i, (n0, _) in enumerate(groups)}
+        ends = {n1 - 1: i for i, (_, n1) in enumerate(groups)}
         for n in range(w.steps):
             out = 1 + n % 3
-            if events is not None:
-                events[n][0].record()
+            if events is not None and n in starts:
+                events[starts[n]][0].record()
             self.runner.step(n, prev, cur, out)
-            if events is not None:
-                events[n][1].record()
+            if events is not None and n in ends:
+                events[ends[n]][1].record()
             prev, cur = cur, out
             if w.nu_every and (n + 1) % w.nu_every == 0:
                 c.nusselt(self.ring[cur], self.w_, profile=self.prof[q], sync=False)
@@ -114,20 +123,24 @@ class Run:
 
 
 def time_runs(run, k, warmup, kernel_times=None):
-    """Wall time of k whole runs after warm-up; per-step kernel times (ms) from
-    event pairs recorded around each step launch are appended to kernel_times."""
+    """Wall time of k whole runs after warm-up.  With kernel_times, the step
+    kernel's time (ms per launch) of every range of back-to-back step launches,
+    from an event pair around the range, is appended once per launch."""
     for _ in range(warmup):
         run.run()
     torch.cuda.synchronize()
+    groups = run.step_groups()
     pools = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(run.w.steps)] for _ in range(k)]
+              for _ in groups] for _ in range(k)]
     t0 = time.perf_counter()
     for r in range(k):
         run.run(pools[r] if kernel_times is not None else None)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     if kernel_times is not None:
-        kernel_times.extend(a.elapsed_time(b) for pool in pools for a, b in pool)
+        for pool in pools:
+            for (a, b), (n0, n1) in zip(pool, groups):
+                kernel_times.extend([a.elapsed_time(b) / (n1 - n0)] * (n1 - n0))
     return el
 
 
