@@ -614,7 +614,13 @@ void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 
     launch_one<T, LL, MODE, R, MB, PF, false, false, false>(grid, block, s, a);
   } else {
     if (walls) launch_eo<T, LL, MODE, R, MB, PF, true>(expz, ord4, grid, block, s, a);
-    else if (uxy && !expz && !ord4) launch_one<T, LL, MODE, R, MB, PF, false, false, false, true>(grid, block, s, a);
+    else if (uxy && !expz && !ord4) {
+      // the plain forward step in FP32 runs two levels of loads ahead: 1-3%
+      // faster, and with no spills up to 36-level chunks (the other variants
+      // spill at that depth)
+      constexpr int PFU = (sizeof(T) == 4 && MODE == FWD && LL <= 36) ? 2 : PF;
+      launch_one<T, LL, MODE, R, MB, PFU, false, false, false, true>(grid, block, s, a);
+    }
     else launch_eo<T, LL, MODE, R, MB, PF, false>(expz, ord4, grid, block, s, a);
   }
 }
