@@ -615,10 +615,10 @@ void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 
   } else {
     if (walls) launch_eo<T, LL, MODE, R, MB, PF, true>(expz, ord4, grid, block, s, a);
     else if (uxy && !expz && !ord4) {
-      // the plain forward step in FP32 runs two levels of loads ahead: 1-3%
-      // faster, and with no spills up to 36-level chunks (the other variants
-      // spill at that depth)
-      constexpr int PFU = (sizeof(T) == 4 && MODE == FWD && LL <= 36) ? 2 : PF;
+      // the plain FP32 step runs two levels of loads ahead (forward with chunks
+      // of up to 36 levels: 1-3% faster; reverse with chunks of 32: 1%); those
+      // kernels do not spill at that depth, the other variants do
+      constexpr int PFU = (sizeof(T) == 4 && ((MODE == FWD && LL <= 36) || (MODE == BWD && LL == 32))) ? 2 : PF;
       launch_one<T, LL, MODE, R, MB, PFU, false, false, false, true>(grid, block, s, a);
     }
     else launch_eo<T, LL, MODE, R, MB, PF, false>(expz, ord4, grid, block, s, a);
