@@ -308,6 +308,27 @@ def test_adjoint_parity(nsteps, n_avg, stretch_x):
         assert rel_max(a, b) <= 1e-11
 
 
+@pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (7, 1), (7, 16), (6, 3), (1, 3), (5, 5)])
+def test_rollout_checkpoint_segments(nsteps, ckpt):
+    """The autograd rollout (checkpoint pairs and the last segment kept by the
+    forward pass, the other segments recomputed) against the oracle's discrete
+    adjoint, for segment counts of one to seven, a ragged last segment and a
+    single step (FP64)."""
+    print("case rollout", nsteps, ckpt, flush=True)
+    from paper_1805_03426_amd.autograd import rollout
+    case = Case((8, 6, 7), (2, 3, 2), 1.5, ra=1e4, kmax=2, n_avg=3)
+    target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, nsteps, target)
+    with case.ctx() as ctx:
+        th = case.d(case.th0).requires_grad_(True)
+        U, V, W = (case.d(a).requires_grad_(True) for a in (case.U, case.V, case.W))
+        out = rollout(ctx, th, U, V, W, nsteps, ckpt)
+        torch.autograd.backward(out, out.detach() - case.d(target))
+        got = [host(t.grad) for t in (th, U, V, W)]
+    for a, b in zip(got, (w0, wU, wV, wW)):
+        assert rel_max(a, b) <= 1e-11
+
+
 def test_refine_transpose_dot_product():
     """<P x, y> = <x, P^T y> on the GPU (FP64), ragged grid."""
     print("case refine transpose", flush=True)
