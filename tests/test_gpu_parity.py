@@ -308,6 +308,20 @@ def test_adjoint_parity(nsteps, n_avg, stretch_x):
         assert rel_max(a, b) <= 1e-11
 
 
+@pytest.mark.parametrize("stretch_x", [False, True])
+def test_adjoint_parity_fp32(stretch_x):
+    """FP32 reverse sweep (the uniform-width kernels with two levels of
+    prefetch, and the general kernels on stretched x) against the oracle's
+    FP64 discrete adjoint: relative L2 within the FP32 step bar."""
+    print("case adjoint fp32", stretch_x, flush=True)
+    case = Case((8, 6, 7), (2, 3, 2), 1.5, ra=1e4, kmax=2, n_avg=3, precision="fp32", stretch_x=stretch_x)
+    target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, 6, target)
+    got = _gpu_loss_grad(case, 6, target)
+    for a, b in zip(got, (w0, wU, wV, wW)):
+        assert rel_l2(a, b) <= FP32_TOL
+
+
 @pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (7, 1), (7, 16), (6, 3), (1, 3), (5, 5)])
 def test_rollout_checkpoint_segments(nsteps, ckpt):
     """The autograd rollout (checkpoint pairs and the last segment kept by the
