@@ -72,3 +72,37 @@ def test_rb256_side_walls():
         assert rel_max(gw, ww) <= FP64_TOL
         assert np.all(gu[:, :, 0] == 0) and np.all(gv[:, 0] == 0)
         _three_steps(ctx, g, p, d, (u, v, ww), du)
+
+
+def test_rb256_fp32_steps():
+    """The FP32 tier at the full 256^3 size in the launch configuration the
+    benchmark times (8 chunks of 32 levels, one-row patches, two levels of
+    prefetch): refinement and the start-up, leapfrog and averaging steps on
+    the whole field against the FP64 oracle, within the FP32 per-step bar."""
+    print("case rb256 full size fp32", flush=True)
+    import torch
+    from paper_1805_03426_amd.context import Context
+    from tests.test_gpu_parity import FP32_TOL
+    w = WORKLOADS["rb256-m2-fp64"]
+    d = inputs.workload_inputs(w)
+    g = O.Grid(d["xf"], d["yf"], d["zf"], w.m)
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float32)
+    as32 = lambda a: a.astype(np.float32).astype(np.float64)     # the values the GPU holds
+    uvw = O.refine_velocity(g, as32(d["U"]), as32(d["V"]), as32(d["W"]))
+    th0 = as32(d["theta0"])
+    with Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, precision="fp32") as ctx:
+        du = ctx.interpolate_velocity(f32(d["U"]), f32(d["V"]), f32(d["W"]))
+        for a, b in zip(du, uvw):
+            assert rel_l2(host(a), b) <= FP32_TOL
+        out = ctx.empty(ctx.shape_cell)
+        t1 = O.scalar_step(g, p, 0, th0, th0, *uvw)
+        ctx.scalar_step(0, f32(th0), f32(th0), out, *du)
+        assert rel_l2(host(out), t1) <= FP32_TOL
+        t1 = as32(t1)
+        t2 = O.scalar_step(g, p, 1, th0, t1, *uvw)
+        ctx.scalar_step(1, f32(th0), f32(t1), out, *du)
+        assert rel_l2(host(out), t2) <= FP32_TOL
+        t50 = O.scalar_step(g, p, 49, th0, t1, *uvw)
+        ctx.scalar_step(49, f32(th0), f32(t1), out, *du)
+        assert rel_l2(host(out), t50) <= FP32_TOL
