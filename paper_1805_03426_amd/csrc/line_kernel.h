@@ -625,6 +625,41 @@ void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 
   }
 }
 
+// FP64 columns of more than 8 chunks (one 1024-thread workgroup per CU): the
+// plain uniform-width step in one-row patches walked in bands of 4, as in FP32.
+// Timed at 576^3: 12% faster than two-row patches, which stay faster where a
+// column fits 8 chunks (two workgroups per CU: 13% at 256^3).  The other
+// variants spill in that layout, and so do the forward step with chunks of
+// 40 levels and the reverse step with chunks of 36 or 40.
+template <int MODE>
+constexpr bool wide64_ok(int LL) { return MODE == FWD ? LL <= 36 : (MODE == BWD ? LL == 32 : true); }
+
+template <typename T, int MODE>
+hipError_t launch_line_wide64(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
+  constexpr int mb = StepLayout<T>::min_blocks;
+  const int ntx = (c->nx + kWave - 1) / kWave, nty = c->ny;
+  a.band = 4 < ntx ? 4 : ntx;
+  const dim3 grid((unsigned)(ntx * nty));
+  const dim3 block(kWave, c->nch);
+  switch (c->L) {
+#define MR_CASE(LL)                                                                             \
+  case LL:                                                                                      \
+    if constexpr (wide64_ok<MODE>(LL)) {                                                        \
+      launch_one<T, LL, MODE, 1, mb, 0, false, false, false, true>(grid, block, s, a);          \
+      break;                                                                                    \
+    } else {                                                                                    \
+      return hipErrorInvalidValue;                                                              \
+    }
+    MR_CASE(32)
+    MR_CASE(36)
+    MR_CASE(40)
+#undef MR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int MODE>
 hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   constexpr int rows = StepLayout<T>::rows, cols = kWave / rows;
@@ -642,6 +677,10 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   a.uhy = (T)c->uhy;
   a.uxx = (T)(c->uhx * c->uhx);
   a.uyy = (T)(c->uhy * c->uhy);
+  if constexpr (sizeof(T) == 8 && MODE != SEED) {
+    if (uxy && !walls && !expz && !ord4 && c->nch > 8 && wide64_ok<MODE>(c->L))
+      return launch_line_wide64<T, MODE>(c, a, s);
+  }
   switch (c->L) {
 #define MR_CASE(LL)                                                                             \
   case LL:                                                                                      \

@@ -195,6 +195,22 @@ def test_step_parity_ragged(nc, m, gamma):
     _step_parity(case, 4, FP64_TOL)
 
 
+@pytest.mark.parametrize("ncz,mz", [(150, 2), (275, 2), (128, 2)])
+def test_step_and_adjoint_parity_deep_columns(ncz, mz):
+    """Uniform x and y with columns of 300 and 550 levels (10 chunks of 32, 16
+    of 36): the FP64 one-row layout for columns of more than 8 chunks, forward
+    (every step type) and reverse; 256 levels (8 chunks) keeps two-row patches."""
+    print("case deep columns", ncz, mz, flush=True)
+    case = Case((5, 3, ncz), (2, 2, mz), 2.0, kmax=1, n_avg=2, random_velocity=True, dt=1e-4)
+    _step_parity(case, 4, FP64_TOL)
+    target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, 4, target)
+    g0, gU, gV, gW = _gpu_loss_grad(case, 4, target)
+    assert rel_max(g0, w0) <= 1e-11
+    for a, b in zip((gU, gV, gW), (wU, wV, wW)):
+        assert rel_max(a, b) <= 1e-11
+
+
 def test_step_fp32_tier_rb64(c1):
     print("case rb64 steps fp32", flush=True)
     case = Case((32, 32, 32), (2, 2, 2), 0.0, ra=1e6, pr=4.38, kmax=8, precision="fp32")
