@@ -1,20 +1,22 @@
 """Benchmark of the multiple-resolution dense-grid scalar step on one MI355X.
 
-One benchmark step is one whole run of the FP64 workload rb256-m2-fp64
-(coarse 128^3 -> dense 256^3, tanh z grid, Ra 1e8, Pr 4.38): refine the
-coarse velocity, check its divergence, then 100 scalar steps with the Nusselt
-profile every 10 steps.  Inputs are resident in HBM before the timed region.
-value = dense-cell updates per second over the whole job.
+One benchmark step is one whole run of the FP64 workload
+rb1024x1024x512-m2-fp64 (coarse 512x512x256 -> dense 1024x1024x512, tanh z
+grid with clustering 2.5, Ra 1e9, Pr 7): refine the coarse velocity, check its
+divergence, then 50 scalar steps with the Nusselt profile every 10 steps.
+This is the largest workload that fits one GPU, in the paper's precision.
+Inputs are resident in HBM before the timed region.  value = dense-cell
+updates per second over the whole job.
 
-Also reported, outside the timed region: the same workload with FP32 storage,
-the adjoint workload (FP32, 20 steps, checkpoint every 5: forward and backward
-times), the inter-grid kernels (integration, Nu_T, refinement in time, one
-coarse step of M_t = 4), the step and refinement with side walls in x and y,
-the step with an explicit z-diffusion share of 1/2 and with fourth-order face
-values, the FP32 step kernel on the 576^3 and
-1024x1024x512 workloads, the copy-kernel bandwidth, the roofline of the
-dominant kernel (the fused scalar step) and the oracle's CPU time on a
-bounded sample.
+Also reported, outside the timed region: the same run with FP32 storage (the
+precision tier on the same grid), the 256^3 FP64 and FP32 runs, the adjoint
+workloads (256^3 and 1024x1024x512, FP32: forward and backward times), the
+inter-grid kernels (integration, Nu_T, refinement in time, one coarse step of
+M_t = 4), the step and refinement with side walls in x and y, the step with an
+explicit z-diffusion share of 1/2 and with fourth-order face values, the step
+kernel on the 576^3 workload in both precisions, the copy-kernel bandwidth,
+the roofline of the dominant kernel (the fused scalar step) and the oracle's
+CPU time on a bounded sample.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -38,10 +40,23 @@ from paper_1805_03426_amd.configs import WORKLOADS  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "dense-cell updates/s per scalar step, % HBM peak; FP32 vs FP64; adjoint/fwd"
-WORKLOAD = "rb256-m2-fp64"
+WORKLOAD = "rb1024x1024x512-m2-fp64"
+SMALL_WORKLOAD = "rb256-m2-fp64"
 ADJOINT_WORKLOAD = "rb256-m2-adjoint-fp32"
+CPU_WORKLOAD = "rb256-m2-fp64"
 STEP_KERNEL = "line_kernel"
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "scalar_step_rb256_fp64_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "scalar_step_rb1024x1024x512_fp64_traffic.md")
+
+_INPUTS = {}
+
+
+def workload_inputs(w):
+    """Seeded host inputs of a workload, generated once per grid (the FP32 and
+    FP64 runs of one grid share them)."""
+    key = (w.nc, w.m, w.gamma, w.kmax, w.cfl, w.urms, w.noise)
+    if key not in _INPUTS:
+        _INPUTS[key] = inputs.workload_inputs(w)
+    return _INPUTS[key]
 
 
 def kernel_source_hash():
@@ -72,7 +87,7 @@ class Run:
 
     def __init__(self, w, precision):
         from paper_1805_03426_amd.context import Context
-        d = inputs.workload_inputs(w)
+        d = workload_inputs(w)
         self.w = w
         self.dt = d["dt"]
         self.ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg,
@@ -284,10 +299,10 @@ def intergrid_times(w, mt=4):
 
 def large_step_times():
     """Scalar-step kernel on the 576^3 (M = 3) workload in FP32 and in FP64 (the
-    precision tier's reference run) and on 1024x1024x512 in FP32: mean kernel
-    time over a few steps and % of HBM peak (6 values per dense cell)."""
+    precision tier's reference run): mean kernel time over a few steps and %
+    of HBM peak (6 values per dense cell)."""
     out = {}
-    for name, prec in (("rb576-m3-fp32", "fp32"), ("rb576-m3-fp32", "fp64"), ("rb1024x1024x512-m2-fp32", "fp32")):
+    for name, prec in (("rb576-m3-fp32", "fp32"), ("rb576-m3-fp32", "fp64")):
         w = WORKLOADS[name]
         r = Run(w, prec)
         c = r.ctx
@@ -310,12 +325,29 @@ def large_step_times():
     return out
 
 
+def whole_runs(w, precision, k, warmup):
+    """k timed whole runs of a workload in a precision: job throughput and the
+    step kernel's mean time and % of HBM peak (6 values per cell)."""
+    r = Run(w, precision)
+    ev = []
+    el = time_runs(r, k, warmup, ev)
+    ms = kernel_ms(ev)
+    vb = 8 if precision == "fp64" else 4
+    out = dict(workload=w.name, precision=precision, value=w.cells * w.steps * k / el,
+               unit="dense-cell updates/s", ms_per_run=el / k * 1e3, step_kernel_ms=ms,
+               step_hbm_frac_alg=6 * vb * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    r.ctx.close()
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
 def walls_times(w):
     """The workload's FP64 step and refinement with adiabatic no-slip side
     walls in x and y (the generator's coarse velocity with its low wall faces
     zeroed): mean kernel times and % of HBM peak."""
     from paper_1805_03426_amd.context import Context
-    d = inputs.workload_inputs(w)
+    d = workload_inputs(w)
     ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, side_x="walls",
                   side_y="walls")
     U, V, W = (torch.from_numpy(d[k]).to("cuda", torch.float64) for k in ("U", "V", "W"))
@@ -344,7 +376,7 @@ def variant_step_times(w, **variant):
     for fourth-order face values): mean kernel time and % of HBM peak (the same
     algorithmic 48 B per cell)."""
     from paper_1805_03426_amd.context import Context
-    d = inputs.workload_inputs(w)
+    d = workload_inputs(w)
     ctx = Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"], n_avg=w.n_avg, **variant)
     U, V, W = (torch.from_numpy(d[k]).to("cuda", torch.float64) for k in ("U", "V", "W"))
     u, v, w_ = ctx.interpolate_velocity(U, V, W)
@@ -362,11 +394,27 @@ def variant_step_times(w, **variant):
     return dict(variant, step_kernel_ms=ms, step_hbm_frac_alg=48 * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
+def host_cpu():
+    """The host's logical CPU count, the threads this process may use, and its
+    CPU model (for the CPU baseline's context)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(nproc=os.cpu_count(), affinity=avail, model=model)
+
+
 def cpu_baseline(w, budget_s=15.0):
-    """The oracle's FP64 scalar step on the same workload, a bounded sample:
-    as many whole-field steps as fit in the budget (at least one)."""
+    """The oracle's FP64 scalar step on a bounded sample: as many whole-field
+    steps of workload w as fit in the budget (at least one).  The oracle is
+    plain NumPy; its elementwise kernels run on one core."""
     import oracle as O
-    d = inputs.workload_inputs(w)
+    d = workload_inputs(w)
     g = O.Grid(d["xf"], d["yf"], d["zf"], w.m)
     p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
     uvw = O.refine_velocity(g, d["U"], d["V"], d["W"])
@@ -381,8 +429,10 @@ def cpu_baseline(w, budget_s=15.0):
             break
     el = time.perf_counter() - t0
     return dict(value=w.cells * n / el, unit="dense-cell updates/s", cores=1, kind="oracle",
-                sample="%d whole-field FP64 scalar steps of %s (%d cells), NumPy single-threaded, %.1f s"
-                       % (n, w.name, w.cells, el))
+                sample="%d whole-field FP64 scalar steps of %s (%d cells; the 1024x1024x512 grid's "
+                       "4.3 GB fields are not run by the oracle), NumPy single-threaded, %.1f s"
+                       % (n, w.name, w.cells, el),
+                host=host_cpu())
 
 
 def main():
@@ -402,7 +452,7 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     w = WORKLOADS[WORKLOAD]
-    print("bench: %s, %d steps + %d warmup" % (w.name, args.steps, args.warmup), file=sys.stderr, flush=True)
+    print("bench: %s, %d runs + %d warmup" % (w.name, args.steps, args.warmup), file=sys.stderr, flush=True)
     run = Run(w, "fp64")
     events = []
     el = time_runs(run, args.steps, args.warmup, events)
@@ -418,33 +468,27 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        print("bench: FP32 tier", file=sys.stderr, flush=True)
-        r32 = Run(w, "fp32")
-        ev32 = []
-        el32 = time_runs(r32, max(1, args.steps), 1, ev32)
-        ms32 = kernel_ms(ev32)
-        extras["fp32"] = dict(value=cells_per_run * max(1, args.steps) / el32, unit="dense-cell updates/s",
-                              step_kernel_ms=ms32,
-                              step_hbm_frac_alg=6 * 4 * w.cells / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS)
-        r32.ctx.close()
-        del r32
-        torch.cuda.empty_cache()
+        print("bench: FP32 tier on the same grid", file=sys.stderr, flush=True)
+        extras["fp32"] = whole_runs(w, "fp32", max(1, args.steps), 1)
+        ws = WORKLOADS[SMALL_WORKLOAD]
+        print("bench: %s FP64 and FP32" % ws.name, file=sys.stderr, flush=True)
+        extras["rb256"] = {prec: whole_runs(ws, prec, max(1, args.steps), 1) for prec in ("fp64", "fp32")}
         print("bench: adjoint", file=sys.stderr, flush=True)
         extras["adjoint"] = adjoint_times()
         torch.cuda.empty_cache()
         print("bench: inter-grid kernels", file=sys.stderr, flush=True)
-        extras["intergrid"] = intergrid_times(w)
+        extras["intergrid"] = intergrid_times(ws)
         torch.cuda.empty_cache()
         print("bench: side walls", file=sys.stderr, flush=True)
-        extras["walls_xy"] = walls_times(w)
+        extras["walls_xy"] = walls_times(ws)
         torch.cuda.empty_cache()
         print("bench: step with an explicit z share", file=sys.stderr, flush=True)
-        extras["z_explicit"] = variant_step_times(w, z_explicit=0.5)
+        extras["z_explicit"] = variant_step_times(ws, z_explicit=0.5)
         torch.cuda.empty_cache()
         print("bench: step with fourth-order faces", file=sys.stderr, flush=True)
-        extras["face_order4"] = variant_step_times(w, face_order=4)
+        extras["face_order4"] = variant_step_times(ws, face_order=4)
         torch.cuda.empty_cache()
-        print("bench: step at 576^3 (FP32, FP64) and 1024x1024x512 (FP32)", file=sys.stderr, flush=True)
+        print("bench: step at 576^3 (FP32, FP64)", file=sys.stderr, flush=True)
         extras["large_steps"] = large_step_times()
         torch.cuda.empty_cache()
         print("bench: adjoint at 1024x1024x512", file=sys.stderr, flush=True)
@@ -463,7 +507,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: CPU baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(WORKLOADS[CPU_WORKLOAD])
 
     line = {
         "metric": METRIC,

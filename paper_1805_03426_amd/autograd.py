@@ -8,8 +8,8 @@ a buffer of its own, so nothing is copied.  Its backward walks the checkpoint
 segments in reverse: it recomputes the states of each segment but the last
 from its checkpoint, runs the fused reverse step of each
 step (transposed implicit solve fused with the transposed stencils), adds the
-segment's dense face-velocity gradient once from the stored (theta^n, mu^n)
-pairs, and finally maps the dense face gradient to the coarse faces with the
+segment's dense face-velocity gradient from the stored (theta^n, mu^n)
+pairs (one library call per group of at most 16 steps), and finally maps the dense face gradient to the coarse faces with the
 transposed refinement.  Every step of the computation is a library call.
 """
 import torch
@@ -23,7 +23,9 @@ class ScalarRollout(torch.autograd.Function):
     def forward(fctx, mr, nsteps, ckpt_every, theta0, U, V, W):
         if nsteps < 1:
             raise ValueError("nsteps must be >= 1")
-        K = max(1, min(int(ckpt_every), MAX_GRAD_STEPS))
+        if int(ckpt_every) != ckpt_every or ckpt_every < 1:
+            raise ValueError("ckpt_every must be a positive integer, got %r" % (ckpt_every,))
+        K = int(ckpt_every)
         u, v, w = mr.interpolate_velocity(U.detach(), V.detach(), W.detach())
         last = ((nsteps - 1) // K) * K          # first step of the last segment
         th0 = theta0.detach().clone()
@@ -92,8 +94,10 @@ class ScalarRollout(torch.autograd.Function):
                 if n == 0:
                     g_theta0 = out
                 mu_next, mu_cur = mu_cur, out
-            idx = list(range(s, e))
-            mr.velocity_grad(idx, [states[n] for n in idx], [mus[n] for n in idx], gu, gv, gw)
+            # one velocity-gradient call per group of at most MAX_GRAD_STEPS steps
+            for g0 in range(s, e, MAX_GRAD_STEPS):
+                idx = list(range(g0, min(g0 + MAX_GRAD_STEPS, e)))
+                mr.velocity_grad(idx, [states[n] for n in idx], [mus[n] for n in idx], gu, gv, gw)
             del states, mus
         gU, gV, gW = mr.interpolate_velocity_backward(gu, gv, gw)
         return None, None, None, g_theta0, gU, gV, gW

@@ -56,4 +56,8 @@ WORKLOADS = {w.name: w for w in [
     # 512x512x256 -> 1024x1024x512, tanh 2.5, Ra 1e9, Pr 7, FP32, forward + adjoint.
     Workload("rb1024x1024x512-m2-fp32", (512, 512, 256), (2, 2, 2), 2.5, 1e9, 7.0, 50, 32, "fp32",
              ckpt_every=10),
+    # The same grid and inputs in FP64, with the Nusselt diagnostics every 10
+    # steps: the largest workload that fits one GPU, in the paper's precision.
+    Workload("rb1024x1024x512-m2-fp64", (512, 512, 256), (2, 2, 2), 2.5, 1e9, 7.0, 50, 32, "fp64",
+             nu_every=10, ckpt_every=10),
 ]}

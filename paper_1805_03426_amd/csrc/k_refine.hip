@@ -643,18 +643,9 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
 }
 
 // U1/V1/W1 null: refine (U, V, W); otherwise refine (1 - frac) (U, V, W) + frac (U1, V1, W1).
-#ifndef MR_FUSED_REFINE
-#define MR_FUSED_REFINE 1
-#endif
-#ifndef MR_FUSED_ROWS
-#define MR_FUSED_ROWS 6
-#endif
-#ifndef MR_FUSED_WGS
-#define MR_FUSED_WGS 8192
-#endif
-#ifndef MR_FUSED_MIN_KC
-#define MR_FUSED_MIN_KC 4
-#endif
+constexpr int kFusedRows = 6;       // most coarse rows per tile
+constexpr int kFusedWgs = 8192;     // workgroups the layer split aims for
+constexpr int kFusedMinKc = 4;      // fewest coarse layers per workgroup
 constexpr size_t kFuseMaxLds = 64 * 1024;
 
 // LDS bytes of refine_fused for a tile of TI x TJ coarse cells.
@@ -674,14 +665,14 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
   while (c->wx && TI >= 2 && c->ncx % TI == 1) --TI;
   if (TI >= 1 && c->mz <= kFuseMaxMz && !(c->wx && TI < 2)) {
     // rows per tile: every stage-z item (one per halo column and row) on its own lane
-    TJ = std::min(std::min(MR_FUSED_ROWS, 256 / (TI + 3) - 2), c->ncy);
+    TJ = std::min(std::min(kFusedRows, 256 / (TI + 3) - 2), c->ncy);
     while (TJ >= 1 && fused_lds<T>(TI, TJ, c->mx, c->my, c->mz) > kFuseMaxLds) --TJ;
     if (c->wy) {
       while (TJ >= 2 && c->ncy % TJ == 1) --TJ;
       if (TJ < 2) TJ = 0;
     }
   }
-  if (MR_FUSED_REFINE && TJ >= 1) {
+  if (TJ >= 1) {
     RefArgs<T> a = ref_args<T>(c, g);
     a.in0 = (const T*)U; a.in1 = (const T*)V; a.in2 = (const T*)W;
     a.in3 = (const T*)U1; a.in4 = (const T*)V1; a.in5 = (const T*)W1;
@@ -690,10 +681,10 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
     const int nbx = (c->ncx + TI - 1) / TI, nby = (c->ncy + TJ - 1) / TJ;
     const int64_t tiles = (int64_t)nbx * nby;
     // coarse layers per workgroup: enough workgroups to fill the chip
-    // (at least MR_FUSED_MIN_KC layers each, so that the table set-up and the first
+    // (at least kFusedMinKc layers each, so that the table set-up and the first
     // layer's loads are shared by a few layers)
-    int nkc = (int)std::max<int64_t>(1, std::min<int64_t>(c->ncz, (MR_FUSED_WGS + tiles - 1) / tiles));
-    nkc = std::min(nkc, std::max(1, c->ncz / MR_FUSED_MIN_KC));
+    int nkc = (int)std::max<int64_t>(1, std::min<int64_t>(c->ncz, (kFusedWgs + tiles - 1) / tiles));
+    nkc = std::min(nkc, std::max(1, c->ncz / kFusedMinKc));
     const int KC = (c->ncz + nkc - 1) / nkc;
     nkc = (c->ncz + KC - 1) / KC;
     const int64_t nb = tiles * nkc;

@@ -131,10 +131,6 @@ __device__ __forceinline__ double lane_shl(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-#ifndef MR_XDPP
-#define MR_XDPP 1
-#endif
-
 // A wavefront covers 64/ROWS columns of ROWS consecutive y rows.  With
 // ROWS > 1 the y neighbours inside the patch are other lanes' centre values
 // (cross-lane shuffles), and one load per field fetches the two halo rows
@@ -176,7 +172,7 @@ template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS, 
           bool UXY = false>
 __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
   static_assert(!((EXPZ || ORD4) && MODE == SEED), "the seed solve has no stencil");
-  static_assert(!ORD4 || (ROWS <= 2 && MR_XDPP), "fourth-order faces need patches of at most two rows");
+  static_assert(!ORD4 || ROWS <= 2, "fourth-order faces need patches of at most two rows");
   static_assert(!UXY || !(WALLS || EXPZ || ORD4), "uniform-width kernels exist for the plain variant only");
   __shared__ double sh[4][kMaxChunks][kWave];
   constexpr int COLS = kWave / ROWS;
@@ -322,15 +318,9 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
       v.zp = ldb(f + min(k + 1, nz - 1) * nxy, oc);
       v.w1 = ldb_nt(A.w + (kc + 1) * nxy, oc);   // used once: z faces are carried
     }
-    if constexpr (MR_XDPP) {
-      v.xm = ldb(fk, oedge);     // edge values, resolved after the lane shifts
-      v.u1 = ldb(uk, oedge_r);
-      v.pxm = ldb(pk, oedge);
-    } else {
-      v.xm = ldb(fk, oxm); v.xp = ldb(fk, oxp);
-      v.u1 = ldb(uk, oxp);
-      v.pxm = ldb(pk, oxm); v.pxp = ldb(pk, oxp);
-    }
+    v.xm = ldb(fk, oedge);     // edge values, resolved after the lane shifts
+    v.u1 = ldb(uk, oedge_r);
+    v.pxm = ldb(pk, oedge);
     v.u0 = ldb(uk, oc);
     v.v0 = ldb(vk, oc); v.v1 = ldb(vk, oyp);
     if constexpr (EXPZ) {
@@ -366,29 +356,27 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
     if (MODE == SEED) {
       r = cur.pc;
     } else {
-      if constexpr (MR_XDPP) {
-        const T fe = cur.xm, pe = cur.pxm, ue = cur.u1;
-        const T fl = lane_shr(zc), fr = lane_shl(zc);
-        const T pl = lane_shr(cur.pc), pr = lane_shl(cur.pc);
-        const T ur = lane_shl(cur.u0);
-        cur.xm = xfirst ? fe : fl;
-        cur.xp = xlast ? fe : fr;
-        cur.pxm = xfirst ? pe : pl;
-        cur.pxp = xlast ? pe : pr;
-        cur.u1 = xlast ? ue : ur;
-        if constexpr (ORD4) {
-          // two lanes over by a cross-lane permute (a second DPP shift on the
-          // first one's result makes the compiler keep every level live)
-          const T e2 = cur.xm2;
-          const T l2 = __shfl(zc, (lane - 2) & (kWave - 1)), r2 = __shfl(zc, (lane + 2) & (kWave - 1));
-          cur.xm2 = x2lo ? e2 : l2;
-          cur.xp2 = x2hi ? e2 : r2;
-          if constexpr (MODE != FWD) {
-            const T eu = cur.um;
-            const T ul = lane_shr(cur.u0), ur2 = __shfl(cur.u1, (lane + 1) & (kWave - 1));
-            cur.um = xfirst ? eu : ul;
-            cur.up2 = xlast ? eu : ur2;
-          }
+      const T fe = cur.xm, pe = cur.pxm, ue = cur.u1;
+      const T fl = lane_shr(zc), fr = lane_shl(zc);
+      const T pl = lane_shr(cur.pc), pr = lane_shl(cur.pc);
+      const T ur = lane_shl(cur.u0);
+      cur.xm = xfirst ? fe : fl;
+      cur.xp = xlast ? fe : fr;
+      cur.pxm = xfirst ? pe : pl;
+      cur.pxp = xlast ? pe : pr;
+      cur.u1 = xlast ? ue : ur;
+      if constexpr (ORD4) {
+        // two lanes over by a cross-lane permute (a second DPP shift on the
+        // first one's result makes the compiler keep every level live)
+        const T e2 = cur.xm2;
+        const T l2 = __shfl(zc, (lane - 2) & (kWave - 1)), r2 = __shfl(zc, (lane + 2) & (kWave - 1));
+        cur.xm2 = x2lo ? e2 : l2;
+        cur.xp2 = x2hi ? e2 : r2;
+        if constexpr (MODE != FWD) {
+          const T eu = cur.um;
+          const T ul = lane_shr(cur.u0), ur2 = __shfl(cur.u1, (lane + 1) & (kWave - 1));
+          cur.um = xfirst ? eu : ul;
+          cur.up2 = xlast ? eu : ur2;
         }
       }
       if constexpr (ROWS > 1) {
@@ -559,33 +547,12 @@ __global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
 }
 
 // Patch shape and tile walk per precision (timed on MI355X).
-#ifndef MR_ROWS64
-#define MR_ROWS64 2
-#endif
-#ifndef MR_ROWS32
-#define MR_ROWS32 1
-#endif
-#ifndef MR_BAND64
-#define MR_BAND64 1
-#endif
-#ifndef MR_BAND32
-#define MR_BAND32 4
-#endif
-#ifndef MR_F32_MINB
-#define MR_F32_MINB 1
-#endif
-#ifndef MR_PFD64
-#define MR_PFD64 0
-#endif
-#ifndef MR_PFD32
-#define MR_PFD32 1
-#endif
 template <typename T>
 struct StepLayout {
-  static constexpr int rows = sizeof(T) == 8 ? MR_ROWS64 : MR_ROWS32;
-  static constexpr int band = sizeof(T) == 8 ? MR_BAND64 : MR_BAND32;   // 0: whole rows
-  static constexpr int min_blocks = sizeof(T) == 8 ? 1 : MR_F32_MINB;   // minimum waves per SIMD
-  static constexpr int prefetch = sizeof(T) == 8 ? MR_PFD64 : MR_PFD32;  // levels whose loads run ahead of the arithmetic
+  static constexpr int rows = sizeof(T) == 8 ? 2 : 1;
+  static constexpr int band = sizeof(T) == 8 ? 1 : 4;   // x tiles per band of the walk
+  static constexpr int min_blocks = 1;                  // minimum waves per SIMD
+  static constexpr int prefetch = sizeof(T) == 8 ? 0 : 1;  // levels whose loads run ahead of the arithmetic
 };
 
 // Compile-time variants: side walls, explicit z share, fourth-order faces,

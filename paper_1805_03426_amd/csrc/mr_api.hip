@@ -306,18 +306,11 @@ bool z_factors(int nz, int L, const double* sub, const double* diag, const doubl
   return true;
 }
 
-// Shortest chunk length (at least min_len) that splits nz levels into at most
+// Shortest chunk length that splits nz levels into at most
 // kMaxChunks chunks.
-#ifndef MR_MIN_L64
-#define MR_MIN_L64 32
-#endif
-#ifndef MR_MIN_L32
-#define MR_MIN_L32 32
-#endif
-int choose_chunks(int nz, int precision, int& L, int& nch) {
-  const int min_len = precision == MR_FP64 ? MR_MIN_L64 : MR_MIN_L32;
+int choose_chunks(int nz, int& L, int& nch) {
   for (int l : mr::kChunkLens) {
-    if (l >= min_len && (nz + l - 1) / l <= mr::kMaxChunks) {
+    if ((nz + l - 1) / l <= mr::kMaxChunks) {
       L = l;
       nch = (nz + l - 1) / l;
       return MR_OK;
@@ -540,7 +533,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   int st = check_desc(desc, P);
   if (st != MR_OK) return st;
   int L = 0, nch = 0;
-  if ((st = choose_chunks(P.z.n, desc->precision, L, nch)) != MR_OK) return st;
+  if ((st = choose_chunks(P.z.n, L, nch)) != MR_OK) return st;
 
   vector<double> R[3];
   vector<int> idx[3], start[3];

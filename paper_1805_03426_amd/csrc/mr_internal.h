@@ -171,11 +171,7 @@ inline double alpha_cur(int kind) { return kind == KIND_STARTUP ? 1.0 : (kind ==
 // XCD-aware tile order: the hardware deals consecutive workgroups round-robin
 // to the 8 XCDs; this remaps them so that each XCD walks a contiguous range of
 // tiles (neighbouring rows share that XCD's L2).
-#ifndef MR_XCD_REMAP
-#define MR_XCD_REMAP 1
-#endif
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  if (!MR_XCD_REMAP) return bid;
   constexpr int kXcd = 8;
   const int full = (nblocks / kXcd) * kXcd;
   if (bid >= full) return bid;

@@ -109,8 +109,9 @@ def test_rb576_sampled_and_fp32_drift():
         print("rb576 fp32 vs fp64 after %d steps: theta %.3e, theta-(1-z) %.3e, last increment %.3e; Nu %s"
               % (w.steps, err_theta, err_fluct, err_incr,
                  ", ".join("%s %.2e" % kv for kv in nu_err.items())), flush=True)
-        assert err_theta < 1e-4 and err_fluct < 1e-2
-        assert max(nu_err.values()) < 1e-3
+        # about 10x the measured drift (theta 2.9e-7, fluctuation 1.6e-5, Nu 1.4e-6)
+        assert err_theta < 3e-6 and err_fluct < 2e-4
+        assert max(nu_err.values()) < 1.5e-5
 
 
 def _separable(seed, nx, ny, nz, terms=2):
@@ -289,6 +290,12 @@ def test_adjoint_fp32_against_oracle_rb64():
         out = rollout(c32, th, U, V, W, N, 5)
         torch.autograd.backward(out, out.detach() - _dev(target, torch.float32))
         got = [t.grad.double().cpu().numpy() for t in (th, U, V, W)]
-    for a, b in zip(got, (w0, wU, wV, wW)):
-        e = _rel_l2(a, b)
+    # The bound: the seed theta_N - theta_target is a difference of two O(1)
+    # fields that agree to about 3% (their noise), so its FP32 rounding is
+    # already ~2e-6 relative; each of the 20 reverse steps adds rounding of the
+    # same order (amplification <= 1 per step), and the velocity gradient sums
+    # theta * mu products over all 20 steps.  20 x 2e-6 ~ 4e-5, bounded at 1e-4.
+    errs = [_rel_l2(a, b) for a, b in zip(got, (w0, wU, wV, wW))]
+    print("adjoint rb64 fp32 vs oracle: theta0 %.2e, U %.2e, V %.2e, W %.2e" % tuple(errs), flush=True)
+    for e in errs:
         assert e < 1e-4, e

@@ -225,3 +225,14 @@ def test_init_rejects_levels_beyond_32bit_byte_offsets():
     with pytest.raises(_lib.MRError) as e:
         host_z_system(d64, 0)
     assert e.value.status == _lib.MR_ESHAPE
+
+
+@pytest.mark.parametrize("ckpt", [0, -3, 2.5])
+def test_rollout_rejects_bad_checkpoint_interval(ckpt):
+    """The rollout refuses a checkpoint interval that is not a positive integer
+    before it touches the context or a GPU."""
+    import torch
+    from paper_1805_03426_amd.autograd import rollout
+    t = torch.zeros((2, 2, 2), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        rollout(None, t, t, t, t, 3, ckpt)
