@@ -44,7 +44,7 @@ WORKLOAD = "rb1024x1024x512-m2-fp64"
 SMALL_WORKLOAD = "rb256-m2-fp64"
 ADJOINT_WORKLOAD = "rb256-m2-adjoint-fp32"
 CPU_WORKLOAD = "rb256-m2-fp64"
-STEP_KERNEL = "line_kernel"
+STEP_KERNELS = {"line": "line_kernel", "sweep": "sweep_kernel (with each range's backsub_kernel)"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "scalar_step_rb1024x1024x512_fp64_traffic.md")
 
 _INPUTS = {}
@@ -59,25 +59,27 @@ def workload_inputs(w):
     return _INPUTS[key]
 
 
-def kernel_source_hash():
-    """Hash of the sources that define the scalar-step kernel (its code, the
-    shared header and the host tables and chunk choice), to tell whether the
-    committed counters of that kernel are stale."""
+def kernel_source_hash(method="sweep"):
+    """Hash of the sources that define the step kernel of a method (its code,
+    the shared header and the host tables), to tell whether the committed
+    counters of that kernel are stale."""
+    names = {"sweep": ("k_sweep.hip", "mr_internal.h", "mr_api.hip"),
+             "line": ("line_kernel.h", "k_line_fwd.hip", "k_step.hip", "mr_internal.h", "mr_api.hip")}[method]
     h = hashlib.sha256()
-    for name in ("line_kernel.h", "k_line_fwd.hip", "k_step.hip", "mr_internal.h", "mr_api.hip"):
+    for name in names:
         h.update(open(os.path.join(ROOT, "paper_1805_03426_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """Measured HBM bytes per launch of the step kernel from the committed
+def committed_traffic(method):
+    """Measured HBM bytes per step of the step kernels from the committed
     rocprofv3 counter summary, or None if absent or taken on other sources."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     text = open(PROFILE_TRAFFIC).read()
     m_hash = re.search(r"source hash:\s*([0-9a-f]+)", text)
-    m_bytes = re.search(r"bytes per launch \(scaled\):\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    m_bytes = re.search(r"bytes per step \(scaled\):\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(method):
         return None
     return float(m_bytes.group(1))
 
@@ -112,28 +114,25 @@ class Run:
         return [(n0, min(n0 + g, w.steps)) for n0 in range(0, w.steps, g)]
 
     def run(self, events=None):
-        """One whole run; with ``events`` (a list of (start, end) event pairs,
+        """One whole run: each range of steps between two Nusselt calls is one
+        mr_scalar_steps call (the library picks the fused line solver or the
+        column sweeps).  With ``events`` (a list of (start, end) event pairs,
         one per range of ``step_groups``) it records a pair on the current
-        stream around each range of back-to-back scalar-step launches."""
+        stream around each range's step launches."""
         c, w = self.ctx, self.w
         c.interpolate_velocity(self.U, self.V, self.W, out=(self.u, self.v, self.w_))
         c.divergence(self.u, self.v, self.w_, out=self.div)
         prev = cur = 0
-        q = 0
-        groups = self.step_groups()
-        starts = {n0: i for i, (n0, _) in enumerate(groups)}
-        ends = {n1 - 1: i for i, (_, n1) in enumerate(groups)}
-        for n in range(w.steps):
-            out = 1 + n % 3
-            if events is not None and n in starts:
-                events[starts[n]][0].record()
-            self.runner.step(n, prev, cur, out)
-            if events is not None and n in ends:
-                events[ends[n]][1].record()
-            prev, cur = cur, out
-            if w.nu_every and (n + 1) % w.nu_every == 0:
+        for q, (n0, n1) in enumerate(self.step_groups()):
+            outs = [1 + n % 3 for n in range(n0, n1)]   # ring[0] holds theta^0; three buffers rotate
+            if events is not None:
+                events[q][0].record()
+            self.runner.steps(n0, prev, cur, outs)
+            if events is not None:
+                events[q][1].record()
+            prev, cur = (outs[-2] if len(outs) > 1 else cur), outs[-1]
+            if w.nu_every and n1 % w.nu_every == 0:
                 c.nusselt(self.ring[cur], self.w_, profile=self.prof[q], sync=False)
-                q += 1
         return self.ring[cur]
 
 
@@ -297,27 +296,34 @@ def intergrid_times(w, mt=4):
     return out
 
 
+def sequence_ms(r, count=10, reps=3):
+    """Mean time per step (ms) of step sequences of the given length on a
+    Run's buffers (one mr_scalar_steps call each), after one warm-up call."""
+    state = {"n": 0, "prev": 0, "cur": 0}
+
+    def seq():
+        n0 = state["n"]
+        outs = [1 + n % 3 for n in range(n0, n0 + count)]   # ring[0] holds theta^0
+        r.runner.steps(n0, state["prev"], state["cur"], outs)
+        state.update(n=n0 + count, prev=outs[-2], cur=outs[-1])
+
+    return _event_ms(seq, reps=reps, warmup=1) / count
+
+
 def large_step_times():
-    """Scalar-step kernel on the 576^3 (M = 3) workload in FP32 and in FP64 (the
-    precision tier's reference run): mean kernel time over a few steps and %
-    of HBM peak (6 values per dense cell)."""
+    """The step on the 576^3 (M = 3) workload in FP32 and in FP64 (the
+    precision tier's reference run), in sequences of 10 steps: mean time per
+    step and % of HBM peak (6 values per dense cell)."""
     out = {}
     for name, prec in (("rb576-m3-fp32", "fp32"), ("rb576-m3-fp32", "fp64")):
         w = WORKLOADS[name]
         r = Run(w, prec)
         c = r.ctx
         c.interpolate_velocity(r.U, r.V, r.W, out=(r.u, r.v, r.w_))
-        state = {"n": 0, "prev": 0, "cur": 0}
-
-        def step():
-            n, out = state["n"], 1 + state["n"] % 3   # ring[0] holds theta^0
-            r.runner.step(n, state["prev"], state["cur"], out)
-            state.update(n=n + 1, prev=state["cur"], cur=out)
-
-        ms = _event_ms(step, reps=10, warmup=2)
+        ms = sequence_ms(r)
         nbytes = 6 * (8 if prec == "fp64" else 4) * w.cells
         key = name if prec == "fp32" else name.replace("fp32", "fp64")
-        out[key] = dict(step_kernel_ms=ms, dense_cell_updates_per_s=w.cells / (ms * 1e-3),
+        out[key] = dict(step_method=c.step_method, step_ms=ms, dense_cell_updates_per_s=w.cells / (ms * 1e-3),
                         step_hbm_frac_alg=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         c.close()
         del r
@@ -333,7 +339,8 @@ def whole_runs(w, precision, k, warmup):
     el = time_runs(r, k, warmup, ev)
     ms = kernel_ms(ev)
     vb = 8 if precision == "fp64" else 4
-    out = dict(workload=w.name, precision=precision, value=w.cells * w.steps * k / el,
+    out = dict(workload=w.name, precision=precision, step_method=r.ctx.step_method,
+               value=w.cells * w.steps * k / el,
                unit="dense-cell updates/s", ms_per_run=el / k * 1e3, step_kernel_ms=ms,
                step_hbm_frac_alg=6 * vb * w.cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
     r.ctx.close()
@@ -454,6 +461,7 @@ def main():
     w = WORKLOADS[WORKLOAD]
     print("bench: %s, %d runs + %d warmup" % (w.name, args.steps, args.warmup), file=sys.stderr, flush=True)
     run = Run(w, "fp64")
+    step_kernel = STEP_KERNELS[run.ctx.step_method]
     events = []
     el = time_runs(run, args.steps, args.warmup, events)
     cells_per_run = w.cells * w.steps
@@ -461,7 +469,7 @@ def main():
     ms_step = kernel_ms(events)
     alg_bytes = 6 * 8 * w.cells
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
-    traffic = committed_traffic()
+    traffic = committed_traffic(run.ctx.step_method)
     run.ctx.close()
     del run
     torch.cuda.empty_cache()
@@ -525,7 +533,7 @@ def main():
         "config": {"workload": w.name, "coarse": list(w.nc), "dense": list(w.n), "refinement": list(w.m),
                    "z_tanh": w.gamma, "ra": w.ra, "pr": w.pr, "scalar_steps_per_run": w.steps,
                    "nusselt_every": w.nu_every, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": step_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_kernel_ms": ms_step,
                      "alg_bytes_per_launch": alg_bytes,

@@ -93,6 +93,10 @@ typedef struct {
                               4 = fourth order (Sec. 2.2; the polynomial whose means over the
                               two cells on each side of the face equal their values, only the
                               cells that exist next to a wall); 4 needs uniform x and y widths */
+  int32_t step_method;     /* how step sequences run: 0 = chosen by the library, 1 = the fused
+                              line solver (one kernel per step), 2 = column sweeps (see
+                              mr_scalar_steps; x and y periodic with uniform widths, z_explicit 0,
+                              face order 2 only) */
 } mr_desc;
 
 /* Nusselt summary of one scalar field (Eq. 22, instantaneous). */
@@ -113,12 +117,17 @@ typedef struct {
  * (Sec. 3.2).  Fails with MR_EINVAL on: a non-positive or inconsistent size,
  * refinement factor < 1, fewer than 3 coarse cells on an axis with factor > 1,
  * non-increasing faces, dt <= 0, Ra*Pr <= 0, an unknown wall condition or
- * precision, or an explicit x/y diffusion number
- * 2 dt kappa (4/hx_min^2 + 4/hy_min^2) above 1.  Fails with MR_ESHAPE on sizes
+ * precision, an explicit x/y diffusion number
+ * 2 dt kappa (4/hx_min^2 + 4/hy_min^2) above 1, or column sweeps asked for
+ * where they do not apply.  Fails with MR_ESHAPE on sizes
  * the kernels cannot address: an axis of more than 2^20 dense cells,
  * (N_z + 1) N_x N_y above 2^31 - 1 values, one z level (N_x N_y values of the
  * context's precision) above 2^32 - 1 bytes, or more than 640 z levels (the
- * line solver's 16 chunks of at most 40 levels).  *out is set only on success. */
+ * line solver's 16 chunks of at most 40 levels) unless column sweeps apply
+ * (x and y periodic with uniform widths, z_explicit 0, face order 2) and the
+ * line solver is not asked for: such columns are stepped by column sweeps (see
+ * mr_scalar_steps), and mr_adjoint_seed and mr_scalar_step_backward return
+ * MR_ESHAPE for them.  *out is set only on success. */
 int mr_init(const mr_desc* desc, mr_ctx** out);
 
 /* Free the context and its device tables.  NULL is accepted. */
@@ -162,9 +171,31 @@ int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w,
  *   otherwise (leapfrog):      tau = 2 dt,   a_p = 1,   a_c = 0,   lag = n-1.
  * th_prev is not read at n = 0 (may be NULL).  th_next must not alias th_prev or
  * th_cur: callers rotate three buffers.  The tridiagonal elimination runs in
- * double for both precisions. */
+ * double for both precisions.  One fused line-solver kernel, or with
+ * step_method 2 (and on columns taller than 640 levels) one column sweep and
+ * its back substitution (see mr_scalar_steps). */
 int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_cur, void* th_next,
                    const void* u, const void* v, const void* w, void* stream);
+
+/* Steps n0 .. n0+count-1 in one call: outs[q] (device, count pointers in a
+ * host array) receives theta^{n0+q+1}.  th_prev = theta^{n0-1} (not read at
+ * n0 = 0, may be NULL), th_cur = theta^{n0}.  Every output must differ from
+ * the two levels before it (outs[0] from th_cur and th_prev, outs[1] from
+ * outs[0] and th_cur, outs[q] from outs[q-1] and outs[q-2]): a ring of three
+ * buffers satisfies this.  Results equal count calls of mr_scalar_step to
+ * rounding.
+ * With step_method 2, and with step_method 0 on grids of at least 512 x 512
+ * columns or columns too tall for the line solver (x and y periodic with
+ * uniform widths and the plain method in both cases), the steps run as column
+ * sweeps: each kernel back-substitutes the previous step's implicit solve
+ * while it eliminates its own in the other z direction, so a cell moves
+ * 7 values per step instead of the 6 of one fused step but no column is held
+ * whole on chip.  These sweeps use two elimination fields of the context
+ * (nz*ny*nx values each), allocated on first use and kept until mr_destroy;
+ * MR_EHIP (hipErrorOutOfMemory) if that allocation fails.  In the FP32 tier
+ * the elimination runs in double and its values are stored in float. */
+int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev, const void* th_cur,
+                    void* const* outs, const void* u, const void* v, const void* w, void* stream);
 
 /* ------------------------------------------------------------ adjoint */
 
@@ -282,6 +313,10 @@ int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, 
  * weights for the cells f-2, f-1, f, f+1 (zero for the wall faces and for
  * cells beyond a wall). */
 int mr_host_z_face_weights(const mr_desc* desc, double* w_out);
+
+/* The method mr_scalar_steps uses on this context: 1 = the fused line
+ * solver, 2 = column sweeps. */
+int mr_get_step_method(const mr_ctx* ctx, int32_t* method);
 
 /* Dense sizes of a context and its precision. */
 int mr_get_dims(const mr_ctx* ctx, int32_t* nx, int32_t* ny, int32_t* nz, int32_t* precision);

@@ -22,7 +22,7 @@ EXPORTS = [
     "mr_velocity_grad", "mr_nusselt", "mr_copy_probe", "mr_host_refinement_table",
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
     "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
-    "mr_coarse_step", "mr_host_z_face_weights",
+    "mr_coarse_step", "mr_host_z_face_weights", "mr_scalar_steps", "mr_get_step_method",
 ]
 
 
@@ -40,6 +40,7 @@ class mr_desc(ctypes.Structure):
         ("side_x", c_int32), ("side_y", c_int32),
         ("z_explicit", c_double),
         ("face_order", c_int32),
+        ("step_method", c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ def lib():
         "mr_interpolate_velocity_backward": (c_int, [P, P, P, P, P, P, P, P]),
         "mr_divergence": (c_int, [P, P, P, P, P, P]),
         "mr_scalar_step": (c_int, [P, c_int64, P, P, P, P, P, P, P]),
+        "mr_scalar_steps": (c_int, [P, c_int64, c_int32, P, P, POINTER(c_void_p), P, P, P, P]),
         "mr_adjoint_seed": (c_int, [P, c_int64, P, P, P]),
         "mr_scalar_step_backward": (c_int, [P, c_int64, P, P, P, P, P, P, P, P]),
         "mr_velocity_grad": (c_int, [P, c_int32, POINTER(c_int64), POINTER(c_void_p),
@@ -99,6 +101,7 @@ def lib():
         "mr_host_z_face_weights": (c_int, [POINTER(mr_desc), POINTER(c_double)]),
         "mr_get_dims": (c_int, [P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                 POINTER(c_int32)]),
+        "mr_get_step_method": (c_int, [P, POINTER(c_int32)]),
         "mr_status_string": (c_char_p, [c_int]),
         "mr_last_hip_error": (c_int, [P]),
     }

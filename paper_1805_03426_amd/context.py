@@ -18,16 +18,18 @@ from ._lib import MRError, check, lib, mr_desc, mr_nu
 _BC = {"dirichlet": _lib.MR_DIRICHLET, "adiabatic": _lib.MR_ADIABATIC}
 _PREC = {"fp64": _lib.MR_FP64, "fp32": _lib.MR_FP32}
 _SIDE = {"periodic": _lib.MR_PERIODIC, "walls": _lib.MR_WALLS}
+_METHOD = {"auto": 0, "line": 1, "sweep": 2}
 
 
 def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot="dirichlet",
               bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic",
-              z_explicit=0.0, face_order=2):
+              z_explicit=0.0, face_order=2, step_method="auto"):
     """Build an ``mr_desc``; returns (desc, keepalive) -- keep the second alive
     while the descriptor is in use (it owns the face arrays).  side_x / side_y:
     "periodic" or "walls" (adiabatic no-slip side walls); z_explicit: share w of
     the z diffusion taken explicit on the lagged level (0 to 1/2); face_order:
-    2 (mean of the two cells) or 4 (fourth-order face values, uniform x and y)."""
+    2 (mean of the two cells) or 4 (fourth-order face values, uniform x and y);
+    step_method: "auto", "line" (fused line solver) or "sweep" (column sweeps)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
     mx, my, mz = (int(a) for a in m)
     n = [f.size - 1 for f in faces]
@@ -47,6 +49,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     d.side_x, d.side_y = _SIDE[side_x], _SIDE[side_y]
     d.z_explicit = float(z_explicit)
     d.face_order = int(face_order)
+    d.step_method = _METHOD[step_method]
     return d, faces
 
 
@@ -96,15 +99,16 @@ class Context:
     averaging period n_avg (Eq. 7), the wall conditions and values of the
     scalar, the storage precision ("fp64" or "fp32"), the x and y sides
     ("periodic" or "walls"), the explicit share z_explicit of the z diffusion
-    (0 to 1/2) and the face order of the advection (2 or 4)."""
+    (0 to 1/2), the face order of the advection (2 or 4) and the step method
+    ("auto", "line" or "sweep")."""
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
                  bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
-                 side_y="periodic", z_explicit=0.0, face_order=2):
+                 side_y="periodic", z_explicit=0.0, face_order=2, step_method="auto"):
         if not torch.cuda.is_available():
             raise RuntimeError("the multiple-resolution library needs a HIP GPU")
         desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision,
-                               side_x, side_y, z_explicit, face_order)
+                               side_x, side_y, z_explicit, face_order, step_method)
         self.desc, self._keep = desc, keep
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._ctx = c_void_p()
@@ -256,6 +260,28 @@ class Context:
         check(lib().mr_scalar_step(self._ctx, c_int64(n), *args, _stream()), "mr_scalar_step", self._ctx)
         return out
 
+    def scalar_steps(self, n0, th_prev, th_cur, outs, u, v, w):
+        """Steps n0 .. n0+len(outs)-1: outs[q] receives theta^{n0+q+1} (each
+        output must differ from the two levels before it)."""
+        k = len(outs)
+        if k < 1:
+            raise ValueError("outs must hold at least one buffer")
+        op = (c_void_p * k)(*[self._ptr(t, self.shape_cell, "outs[%d]" % q).value for q, t in enumerate(outs)])
+        args = [self._ptr(th_prev, self.shape_cell, "th_prev") if n0 > 0 else None,
+                self._ptr(th_cur, self.shape_cell, "th_cur"), op,
+                self._ptr(u, self.shape_cell, "u"), self._ptr(v, self.shape_cell, "v"),
+                self._ptr(w, self.shape_w, "w")]
+        check(lib().mr_scalar_steps(self._ctx, c_int64(n0), c_int32(k), *args, _stream()), "mr_scalar_steps",
+              self._ctx)
+        return outs
+
+    @property
+    def step_method(self):
+        """The method step sequences run with: "line" or "sweep"."""
+        m = c_int32()
+        check(lib().mr_get_step_method(self._ctx, byref(m)), "mr_get_step_method", self._ctx)
+        return "sweep" if m.value == 2 else "line"
+
     def step_runner(self, ring, u, v, w):
         """Prepared repeated stepping on fixed buffers: checks the buffers once
         and caches their pointers and the current stream, so each step is one
@@ -341,6 +367,15 @@ class _StepRunner:
         st = self._fn(self._ctx._ctx, n, self._p[a], self._p[b], self._p[c], *self._uvw, self._stream)
         if st:
             check(st, "mr_scalar_step", self._ctx._ctx)
+
+    def steps(self, n0, a, b, outs):
+        """Steps n0 .. n0+len(outs)-1 from ring[a] (level n0-1) and ring[b]
+        (level n0); step n0+q writes ring[outs[q]]."""
+        k = len(outs)
+        op = (c_void_p * k)(*[self._p[q].value for q in outs])
+        st = lib().mr_scalar_steps(self._ctx._ctx, n0, k, self._p[a], self._p[b], op, *self._uvw, self._stream)
+        if st:
+            check(st, "mr_scalar_steps", self._ctx._ctx)
 
 
 def copy_probe(src, dst):

@@ -194,6 +194,7 @@ int refinement_table(const Axis& ax, vector<double>& R, vector<int>& idx, vector
 struct Problem {
   Axis x, y, z;
   double kappa = 0.0;
+  bool sweep_ok = false;   // the column-sweep step applies
 };
 
 int check_desc(const mr_desc* d, Problem& P) {
@@ -217,6 +218,7 @@ int check_desc(const mr_desc* d, Problem& P) {
   // explicit z share: up to 1/2 the z part stays unconditionally stable
   if (!(d->z_explicit >= 0.0 && d->z_explicit <= 0.5)) return MR_EINVAL;
   if (d->face_order != 0 && d->face_order != 2 && d->face_order != 4) return MR_EINVAL;
+  if (d->step_method < 0 || d->step_method > 2) return MR_EINVAL;
   int st;
   if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
   if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
@@ -229,6 +231,13 @@ int check_desc(const mr_desc* d, Problem& P) {
   const double hym = *std::min_element(P.y.h.begin(), P.y.h.end());
   const double num = 2.0 * d->dt * P.kappa * (4.0 / (hxm * hxm) + 4.0 / (hym * hym));
   if (!(num <= 1.0)) return MR_EINVAL;
+  // column sweeps: x and y periodic with uniform widths, the plain method
+  P.sweep_ok = d->side_x == MR_PERIODIC && d->side_y == MR_PERIODIC && uniform_axis(P.x) &&
+               uniform_axis(P.y) && d->z_explicit == 0.0 && d->face_order != 4;
+  if (d->step_method == 2 && !P.sweep_ok) return MR_EINVAL;
+  // columns beyond the line solver's chunks need the sweeps
+  if (nz > (int64_t)mr::kMaxChunks * mr::kChunkLens[2] && (!P.sweep_ok || d->step_method == 1))
+    return MR_ESHAPE;
   return MR_OK;
 }
 
@@ -302,6 +311,37 @@ bool z_factors(int nz, int L, const double* sub, const double* diag, const doubl
     z.Fe[c] = F[k1 - 1];
     z.Gs[c] = z.G[k0];
     z.Bs[c] = z.B[k0];
+  }
+  return true;
+}
+
+// Factors of the column-sweep steps for the system (sub, diag, sup), both
+// elimination directions: upward (the Thomas factors above, back substitution
+// downward) and downward (the mirrored recurrences, back substitution upward).
+struct SweepHost {
+  vector<double> up_m, up_a, up_cb, dn_m, dn_a, dn_cb, tkb;
+};
+
+bool sweep_factors(int nz, const double* sub, const double* diag, const double* sup, SweepHost& z) {
+  z.up_m.assign(nz, 0.0); z.up_a.assign(nz, 0.0); z.up_cb.assign(nz, 0.0);
+  z.dn_m.assign(nz, 0.0); z.dn_a.assign(nz, 0.0); z.dn_cb.assign(nz, 0.0);
+  double c = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double den = diag[k] - (k ? sub[k] * c : 0.0);
+    if (den == 0.0 || !std::isfinite(den)) return false;
+    z.up_m[k] = 1.0 / den;
+    z.up_a[k] = k ? -sub[k] * z.up_m[k] : 0.0;
+    z.up_cb[k] = k < nz - 1 ? sup[k] * z.up_m[k] : 0.0;
+    c = z.up_cb[k];
+  }
+  c = 0.0;
+  for (int k = nz - 1; k >= 0; --k) {
+    const double den = diag[k] - (k < nz - 1 ? sup[k] * c : 0.0);
+    if (den == 0.0 || !std::isfinite(den)) return false;
+    z.dn_m[k] = 1.0 / den;
+    z.dn_a[k] = k < nz - 1 ? -sup[k] * z.dn_m[k] : 0.0;
+    z.dn_cb[k] = k > 0 ? sub[k] * z.dn_m[k] : 0.0;
+    c = z.dn_cb[k];
   }
   return true;
 }
@@ -443,6 +483,27 @@ ZOffsets pack_z(Packer& pk, const ZHost& z) {
   return o;
 }
 
+struct SweepOffsets {
+  size_t up_m, up_a, up_cb, dn_m, dn_a, dn_cb, tkb;
+};
+
+SweepOffsets pack_sweep(Packer& pk, const SweepHost& z) {
+  SweepOffsets o;
+  o.up_m = pk.put(z.up_m); o.up_a = pk.put(z.up_a); o.up_cb = pk.put(z.up_cb);
+  o.dn_m = pk.put(z.dn_m); o.dn_a = pk.put(z.dn_a); o.dn_cb = pk.put(z.dn_cb);
+  o.tkb = pk.put(z.tkb);
+  return o;
+}
+
+mr::SweepSys sweep_ptrs(char* base, const SweepOffsets& o) {
+  mr::SweepSys z;
+  z.up_m = (const double*)(base + o.up_m); z.up_a = (const double*)(base + o.up_a);
+  z.up_cb = (const double*)(base + o.up_cb); z.dn_m = (const double*)(base + o.dn_m);
+  z.dn_a = (const double*)(base + o.dn_a); z.dn_cb = (const double*)(base + o.dn_cb);
+  z.tkb = (const double*)(base + o.tkb);
+  return z;
+}
+
 mr::ZSys z_ptrs(char* base, const ZOffsets& o) {
   mr::ZSys z;
   z.m = (const double*)(base + o.m); z.a = (const double*)(base + o.a); z.cp = (const double*)(base + o.cp);
@@ -480,6 +541,12 @@ const char* mr_status_string(int status) {
 }
 
 int mr_last_hip_error(const mr_ctx* ctx) { return ctx ? ctx->last_err : 0; }
+
+int mr_get_step_method(const mr_ctx* ctx, int32_t* method) {
+  if (!ctx || !method) return MR_EINVAL;
+  *method = ctx->sweep_pref ? 2 : 1;
+  return MR_OK;
+}
 
 int mr_get_dims(const mr_ctx* ctx, int32_t* nx, int32_t* ny, int32_t* nz, int32_t* precision) {
   if (!ctx) return MR_EINVAL;
@@ -533,7 +600,10 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   int st = check_desc(desc, P);
   if (st != MR_OK) return st;
   int L = 0, nch = 0;
-  if ((st = choose_chunks(P.z.n, L, nch)) != MR_OK) return st;
+  // columns taller than the line solver's chunks: only the column-sweep step
+  // (check_desc has made sure that it applies)
+  if (choose_chunks(P.z.n, L, nch) != MR_OK) L = nch = 0;
+  const int npad = std::max(nch * L, P.z.n);
 
   vector<double> R[3];
   vector<int> idx[3], start[3];
@@ -542,9 +612,10 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     if ((st = refinement_table(*axes[a], R[a], idx[a], start[a])) != MR_OK) return st;
 
   Packer pk;
-  GeomOffsets o64 = pack_geom<double>(pk, P, desc, R, idx, nch * L);
-  GeomOffsets o32 = pack_geom<float>(pk, P, desc, R, idx, nch * L);
+  GeomOffsets o64 = pack_geom<double>(pk, P, desc, R, idx, npad);
+  GeomOffsets o32 = pack_geom<float>(pk, P, desc, R, idx, npad);
   ZOffsets zfo[mr::NKINDS], zto[mr::NKINDS];
+  SweepOffsets swo[mr::NKINDS];
   double taus[mr::NKINDS];
   const int nz = P.z.n;
   vector<double> sub(nz), diag(nz), sup(nz), bz(nz), tsub(nz), tsup(nz);
@@ -554,6 +625,12 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     const double tk = tau * P.kappa;
     // the implicit share (1 - w) of the z diffusion; the wall source stays whole
     z_system(P.z, desc, tk * (1.0 - desc->z_explicit), sub.data(), diag.data(), sup.data(), bz.data());
+    SweepHost sh;
+    if (!sweep_factors(nz, sub.data(), diag.data(), sup.data(), sh)) return MR_EINVAL;
+    sh.tkb.assign(nz, 0.0);
+    for (int k = 0; k < nz; ++k) sh.tkb[k] = tk * bz[k];
+    swo[kind] = pack_sweep(pk, sh);
+    if (nch == 0) continue;
     ZHost zh, th;
     if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
     zh.tkb.assign((size_t)nch * L, 0.0);
@@ -613,9 +690,19 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   c->g64 = geom_ptrs<double>(base, o64);
   c->g32 = geom_ptrs<float>(base, o32);
   for (int k = 0; k < mr::NKINDS; ++k) {
-    c->zf[k] = z_ptrs(base, zfo[k]);
-    c->zt[k] = z_ptrs(base, zto[k]);
+    if (nch > 0) {
+      c->zf[k] = z_ptrs(base, zfo[k]);
+      c->zt[k] = z_ptrs(base, zto[k]);
+    }
+    c->sw[k] = sweep_ptrs(base, swo[k]);
   }
+  // step sequences run as column sweeps where the line solver cannot take the
+  // columns, and on grids of at least 512 x 512 columns, where the sweep's
+  // tiles fill the GPU
+  c->sweep_pref = desc->step_method == 2 ||
+                  (desc->step_method == 0 && P.sweep_ok &&
+                   (nch == 0 || (int64_t)c->nx * c->ny >= (int64_t)512 * 512));
+  c->sweep_single = nch == 0 || desc->step_method == 2;
   c->hx64 = (const double*)(base + o_hx64);
   c->areaw = (const double*)(base + o_hy64);
   c->dcz = (const double*)(base + o_dcz);
@@ -630,6 +717,8 @@ int mr_destroy(mr_ctx* ctx) {
   if (ctx->interp_tmp) (void)hipFree(ctx->interp_tmp);
   if (ctx->interp_bwd_tmp) (void)hipFree(ctx->interp_bwd_tmp);
   if (ctx->red) (void)hipFree(ctx->red);
+  for (void* p : ctx->sweep_e)
+    if (p) (void)hipFree(p);
   delete ctx;
   return MR_OK;
 }
@@ -666,13 +755,44 @@ int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_c
   if (!ctx || n < 0 || !th_cur || !th_next || !u || !v || !w) return MR_EINVAL;
   if (n > 0 && !th_prev) return MR_EINVAL;
   if (th_next == th_cur || th_next == th_prev) return MR_EINVAL;
-  MR_LAUNCH(mr::launch_step(ctx, n, n > 0 ? th_prev : th_cur, th_cur, th_next, u, v, w,
-                            as_stream(stream)));
+  const void* thp = n > 0 ? th_prev : th_cur;
+  if (ctx->sweep_single) {
+    // one column sweep and its back substitution
+    void* outs[1] = {th_next};
+    MR_LAUNCH(mr::launch_sweep_steps(ctx, n, 1, thp, th_cur, outs, u, v, w, as_stream(stream)));
+    return MR_OK;
+  }
+  MR_LAUNCH(mr::launch_step(ctx, n, thp, th_cur, th_next, u, v, w, as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev, const void* th_cur,
+                    void* const* outs, const void* u, const void* v, const void* w, void* stream) {
+  if (!ctx || n0 < 0 || count < 1 || !th_cur || !outs || !u || !v || !w) return MR_EINVAL;
+  if (n0 > 0 && !th_prev) return MR_EINVAL;
+  const void* thp = n0 > 0 ? th_prev : th_cur;
+  // every output differs from the two levels before it
+  for (int32_t q = 0; q < count; ++q) {
+    const void* l1 = q >= 1 ? outs[q - 1] : th_cur;
+    const void* l2 = q >= 2 ? outs[q - 2] : (q == 1 ? th_cur : thp);
+    if (!outs[q] || outs[q] == l1 || outs[q] == l2) return MR_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  if (ctx->sweep_pref) {
+    MR_LAUNCH(mr::launch_sweep_steps(ctx, n0, count, thp, th_cur, outs, u, v, w, s));
+    return MR_OK;
+  }
+  for (int32_t q = 0; q < count; ++q) {
+    const void* a = q >= 2 ? outs[q - 2] : (q == 1 ? th_cur : thp);
+    const void* b = q >= 1 ? outs[q - 1] : th_cur;
+    MR_LAUNCH(mr::launch_step(ctx, n0 + q, a, b, outs[q], u, v, w, s));
+  }
   return MR_OK;
 }
 
 int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream) {
   if (!ctx || n < 0 || !lam || !mu_out || lam == mu_out) return MR_EINVAL;
+  if (ctx->nch == 0) return MR_ESHAPE;
   MR_LAUNCH(mr::launch_seed(ctx, n, lam, mu_out, as_stream(stream)));
   return MR_OK;
 }
@@ -682,6 +802,7 @@ int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const v
                             const void* w, void* stream) {
   if (!ctx || n < 0 || !mu_cur || !out || !u || !v || !w) return MR_EINVAL;
   if (out == mu_cur || (mu_next && out == mu_next) || (lam_add && out == lam_add)) return MR_EINVAL;
+  if (ctx->nch == 0) return MR_ESHAPE;
   MR_LAUNCH(mr::launch_step_backward(ctx, n, mu_next, mu_cur, lam_add, out, u, v, w,
                                      as_stream(stream)));
   return MR_OK;
@@ -761,14 +882,38 @@ int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const vo
     return MR_EINVAL;
   if (n0 == 0) p = c;
   hipStream_t s = as_stream(stream);
-  for (int32_t i = 1; i <= mt; ++i) {
-    MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
-    const int64_t n = n0 + i - 1;
+  if (ctx->sweep_pref) {
+    // column sweeps: the kernel of sub-step i finishes theta^{n0+i-1} and
+    // starts sub-step i on the velocity refined just before it
+    const int c0 = c;
+    for (int32_t i = 1; i <= mt; ++i) {
+      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
+      const int q = i - 1;
+      int o = 0;
+      while (o == c || o == p) ++o;
+      // q = 0 reads theta^{n0} itself; q > 0 writes theta^{n0+q} into the free buffer
+      MR_LAUNCH(mr::launch_sweep_step(ctx, n0, q, q == 0 ? ring[p] : ring[c], ring[c0],
+                                      q == 0 ? nullptr : ring[o], u, v, w, s));
+      if (q > 0) {
+        p = c;
+        c = o;
+      }
+    }
     int o = 0;
-    while (o == c || o == p) ++o;   // the buffer holding neither level
-    MR_LAUNCH(mr::launch_step(ctx, n, ring[p], ring[c], ring[o], u, v, w, s));
+    while (o == c || o == p) ++o;
+    MR_LAUNCH(mr::launch_sweep_finish(ctx, n0, mt, ring[o], s));
     p = c;
     c = o;
+  } else {
+    for (int32_t i = 1; i <= mt; ++i) {
+      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
+      const int64_t n = n0 + i - 1;
+      int o = 0;
+      while (o == c || o == p) ++o;   // the buffer holding neither level
+      MR_LAUNCH(mr::launch_step(ctx, n, ring[p], ring[c], ring[o], u, v, w, s));
+      p = c;
+      c = o;
+    }
   }
   if (theta_c) MR_LAUNCH(mr::launch_integrate(ctx, ring[c], theta_c, s));
   *prev = p;

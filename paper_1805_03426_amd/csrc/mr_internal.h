@@ -71,6 +71,22 @@ struct ZSys {
   const double* tkb; // tau kappa b_z (wall source); zeros for the transpose
 };
 
+// Factors of the implicit z system of one step type for the column-sweep
+// kernels, both elimination directions (nz rows each):
+//   upward:   e_k = up_m_k (r_k + tkb_k) + up_a_k e_{k-1}, then downward
+//             x_k = e_k - up_cb_k x_{k+1};
+//   downward: e_k = dn_m_k (r_k + tkb_k) + dn_a_k e_{k+1}, then upward
+//             x_k = e_k - dn_cb_k x_{k-1}.
+struct SweepSys {
+  const double* up_m;
+  const double* up_a;
+  const double* up_cb;
+  const double* dn_m;
+  const double* dn_a;
+  const double* dn_cb;
+  const double* tkb;
+};
+
 }  // namespace mr
 
 struct mr_ctx {
@@ -85,7 +101,8 @@ struct mr_ctx {
   int face_order;                  // face value of the advected scalar: 2 or 4
   int device;
   int last_err;
-  int L, nch;                      // z chunk length and count of the line solver
+  int L, nch;                      // z chunk length and count of the line solver (0: columns too
+                                   // tall for it; only the column-sweep step runs)
   double atot;                     // total horizontal area
   double vtot;                     // domain volume (atot times the height)
   double tau[mr::NKINDS];
@@ -94,6 +111,10 @@ struct mr_ctx {
   mr::Geom<float> g32;
   mr::ZSys zf[mr::NKINDS];         // forward systems per step kind
   mr::ZSys zt[mr::NKINDS];         // transposed systems per step kind
+  mr::SweepSys sw[mr::NKINDS];     // column-sweep factors per step kind
+  int sweep_pref;                  // run step sequences as column sweeps
+  int sweep_single;                // run single steps as a column sweep and its back substitution
+  void* sweep_e[2];                // elimination values of two consecutive sweep steps (lazy)
   const double* areaw;             // [ny] hy_j (area = hx_i * hy_j, built in kernel)
   const double* hx64;              // [nx]
   const double* dcz;               // [nz+1] centre distances across z faces (wall: half cell)
@@ -130,6 +151,17 @@ hipError_t launch_refine_time(mr_ctx* c, const void* U0, const void* V0, const v
                               void* v, void* w, hipStream_t s);
 hipError_t launch_integrate(mr_ctx* c, const void* th, void* tc, hipStream_t s);
 hipError_t launch_dissipation(mr_ctx* c, const void* th, double* out, hipStream_t s);
+// Column-sweep steps n0 .. n0+count-1 (outs[q] receives theta^{n0+q+1}).
+// One sweep kernel per step: step n0 + q (q = 0 reads theta^{n0} from src0 and
+// writes no scalar; q > 0 writes theta^{n0+q} into th_out), then one back
+// substitution of the last step into out.
+bool sweep_supported(const mr_ctx* c);
+hipError_t launch_sweep_step(mr_ctx* c, int64_t n0, int q, const void* lag, const void* src0,
+                             void* th_out, const void* u, const void* v, const void* w, hipStream_t s);
+hipError_t launch_sweep_finish(mr_ctx* c, int64_t n0, int count, void* out, hipStream_t s);
+hipError_t launch_sweep_steps(mr_ctx* c, int64_t n0, int count, const void* thp, const void* thc,
+                              void* const* outs, const void* u, const void* v, const void* w,
+                              hipStream_t s);
 // Grows the context's reduction scratch to at least `bytes`.
 hipError_t ensure_red(mr_ctx* c, size_t bytes);
 

@@ -41,21 +41,31 @@ def refine_window(U, V, W, m, zf, nx, ny, I, J):
     return (u, v, w), ((I - r) * mx, (J - r) * my)
 
 
-def step_column(th_prev, th_cur, uvw_window, origin, zf, nx, ny, m, params, n, i, j):
-    """Oracle scalar step n for dense column (i, j): a 3x3-column window of the
-    scalar levels and of the window velocity around (i, j)."""
+def window3(a, nx, ny, i, j):
+    """The nz x 3 x 3 columns of field a around dense column (i, j), wrapped."""
+    xs = np.arange(i - 1, i + 2) % nx
+    ys = np.arange(j - 1, j + 2) % ny
+    return _take(_take(a, 2, xs), 1, ys)
+
+
+def step_column_windows(tp, tc, uvw_window, origin, zf, nx, ny, params, n, i, j):
+    """Oracle scalar step n for dense column (i, j) from nz x 3 x 3 windows
+    (centred on the column) of theta^{n-1} and theta^n and the window velocity."""
     u, v, w = uvw_window
     ox, oy = origin
     li, lj = i - ox, j - oy            # position inside the velocity window
     assert 1 <= li < u.shape[2] - 1 and 1 <= lj < u.shape[1] - 1
-    xs = np.arange(i - 1, i + 2) % nx
-    ys = np.arange(j - 1, j + 2) % ny
-    tp = _take(_take(th_prev, 2, xs), 1, ys)
-    tc = _take(_take(th_cur, 2, xs), 1, ys)
     sl = (slice(None), slice(lj - 1, lj + 2), slice(li - 1, li + 2))
     g = O.Grid(np.arange(4) / nx, np.arange(4) / ny, zf, (1, 1, 1))
     out = O.scalar_step(g, params, n, tp, tc, u[sl], v[sl], w[sl])
     return out[:, 1, 1]
+
+
+def step_column(th_prev, th_cur, uvw_window, origin, zf, nx, ny, m, params, n, i, j):
+    """Oracle scalar step n for dense column (i, j): a 3x3-column window of the
+    scalar levels and of the window velocity around (i, j)."""
+    return step_column_windows(window3(th_prev, nx, ny, i, j), window3(th_cur, nx, ny, i, j), uvw_window,
+                               origin, zf, nx, ny, params, n, i, j)
 
 
 def dense_column(uvw_window, origin, i, j):

@@ -25,6 +25,18 @@ from tests import sampling as S
 pytestmark = pytest.mark.gpu
 
 
+_INPUTS = {}
+
+
+def _inputs(w):
+    """Seeded generator inputs of a workload, built once per grid in this module."""
+    key = (w.nc, w.m, w.gamma, w.kmax, w.cfl, w.urms, w.noise)
+    if key not in _INPUTS:
+        _INPUTS.clear()
+        _INPUTS[key] = inputs.workload_inputs(w)
+    return _INPUTS[key]
+
+
 def _ctx(d, w, precision, n_avg=None):
     from paper_1805_03426_amd.context import Context
     return Context(d["xf"], d["yf"], d["zf"], w.m, w.ra, w.pr, d["dt"],
@@ -200,7 +212,7 @@ def test_rb1024_fp32_sampled():
     (seed, reverse steps, velocity gradient) on sampled columns."""
     print("case rb1024x1024x512 fp32 full size", flush=True)
     w = WORKLOADS["rb1024x1024x512-m2-fp32"]
-    d = inputs.workload_inputs(w)
+    d = _inputs(w)
     nx, ny, nz = w.n
     cols = S.sample_columns(nx, ny, w.m[0], w.m[1], 5, seed=12)
     th0 = d["theta0"]
@@ -210,6 +222,55 @@ def test_rb1024_fp32_sampled():
         print("rb1024x1024x512 sampled: refine %.2e step %.2e" % (r, s), flush=True)
         b = _sampled_backward_checks(w, d, c32, cols, uvw, 1e-5)
     print("rb1024x1024x512 sampled reverse pass: %.2e" % b, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rb1024_step_sequences_sampled(prec):
+    """1024x1024x512 in the benchmark's launch configuration (step sequences
+    as column sweeps): a sequence of the start-up and two leapfrog steps, then
+    a sequence across the averaging step (48, 49, 50), every output level on
+    sampled columns against the windowed oracle from the GPU's own two input
+    levels (FP64 1e-12, FP32 1e-5 relative L2)."""
+    print("case rb1024x1024x512 step sequences", prec, flush=True)
+    w = WORKLOADS["rb1024x1024x512-m2-" + prec]
+    d = _inputs(w)
+    nx, ny, nz = w.n
+    mx, my, _ = w.m
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    cols = S.sample_columns(nx, ny, mx, my, 5, seed=13)
+    p = O.ScalarParams.from_ra_pr(w.ra, w.pr, d["dt"], n_avg=w.n_avg)
+    windows = {c: S.refine_window(d["U"], d["V"], d["W"], w.m, d["zf"], nx, ny, c[0] // mx, c[1] // my)
+               for c in cols}
+
+    def win(t, i, j):
+        xs = torch.tensor(np.arange(i - 1, i + 2) % nx, device="cuda")
+        ys = torch.tensor(np.arange(j - 1, j + 2) % ny, device="cuda")
+        return t.index_select(1, ys).index_select(2, xs).double().cpu().numpy()
+
+    worst = 0.0
+    with _ctx(d, w, prec) as ctx:
+        u, v, wv = ctx.interpolate_velocity(_dev(d["U"], dtype), _dev(d["V"], dtype), _dev(d["W"], dtype))
+        th0 = _dev(d["theta0"], dtype)
+        ring = [ctx.empty(ctx.shape_cell) for _ in range(3)]
+        ctx.scalar_steps(0, None, th0, ring, u, v, wv)
+        seqs = [(0, [th0, th0, ring[0], ring[1], ring[2]])]
+        # steps 48, 49 (averaging) and 50 from (theta^2, theta^3) of the first sequence
+        extra = [ctx.empty(ctx.shape_cell) for _ in range(3)]
+        ctx.scalar_steps(48, ring[1], ring[2], extra, u, v, wv)
+        seqs.append((48, [ring[1], ring[2]] + extra))
+        torch.cuda.synchronize()
+        for n0, lv in seqs:
+            for q in range(3):
+                got, want = [], []
+                for (i, j) in cols:
+                    got.append(lv[q + 2][:, j, i].double().cpu().numpy())
+                    want.append(S.step_column_windows(win(lv[q], i, j), win(lv[q + 1], i, j), *windows[(i, j)],
+                                                      d["zf"], nx, ny, p, n0 + q, i, j))
+                e = _rel_l2(np.stack(got), np.stack(want))
+                worst = max(worst, e)
+                assert e <= tol, (n0 + q, e)
+    print("rb1024x1024x512 %s step sequences sampled: %.2e" % (prec, worst), flush=True)
 
 
 def _fp64_loss(c64, d, th0, U, V, W, N, target):

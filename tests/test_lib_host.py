@@ -186,12 +186,53 @@ def test_init_rejects_large_diffusion_number():
     assert _lib.lib().mr_init(ctypes.byref(d), ctypes.byref(ctx)) == _lib.MR_EINVAL
 
 
-def test_init_rejects_too_many_z_levels():
-    """More z levels than the line solver's 16 chunks x 40 levels is MR_ESHAPE."""
+@pytest.mark.parametrize("kw", [dict(side_x="walls"), dict(step_method="line"), dict(z_explicit=0.5),
+                                dict(face_order=4)])
+def test_init_rejects_too_many_z_levels(kw):
+    """More z levels than the line solver's 16 chunks x 40 levels is MR_ESHAPE
+    unless the column sweeps apply (periodic uniform x and y, the plain method)
+    and the line solver is not asked for."""
     xf = inputs.uniform_faces(8)
-    d, keep = make_desc(xf, xf, inputs.uniform_faces(642), (2, 2, 2), ra=1e6, pr=1.0, dt=1e-5)
+    d, keep = make_desc(xf, xf, inputs.uniform_faces(642), (2, 2, 2), ra=1e6, pr=1.0, dt=1e-5, **kw)
     ctx = ctypes.c_void_p()
     assert _lib.lib().mr_init(ctypes.byref(d), ctypes.byref(ctx)) == _lib.MR_ESHAPE
+    with pytest.raises(_lib.MRError) as e:
+        host_z_system(d, 0)
+    assert e.value.status == _lib.MR_ESHAPE
+
+
+def test_tall_columns_accepted_for_column_sweeps():
+    """1024 z levels on periodic uniform x and y with the plain method: the
+    descriptor is valid (column sweeps), in both precisions and step methods
+    "auto" and "sweep"."""
+    xf = inputs.uniform_faces(8)
+    for prec in ("fp64", "fp32"):
+        for method in ("auto", "sweep"):
+            d, keep = make_desc(xf, xf, inputs.tanh_faces(1024, 2.0), (2, 2, 2), ra=1e6, pr=1.0, dt=1e-5,
+                                precision=prec, step_method=method)
+            sub, diag, sup, bz, tau = host_z_system(d, 0)
+            assert diag.shape == (1024,) and tau == 1e-5
+
+
+@pytest.mark.parametrize("kw", [dict(side_y="walls"), dict(z_explicit=0.25), dict(face_order=4),
+                                dict(stretch=True)])
+def test_column_sweeps_refused_where_they_do_not_apply(kw):
+    """step_method "sweep" needs periodic uniform x and y and the plain method (MR_EINVAL)."""
+    kw = dict(kw)
+    xf = inputs.uniform_faces(12)
+    if kw.pop("stretch", False):
+        xf = np.concatenate([[0.0], np.cumsum(np.linspace(1.0, 2.0, 12))])
+        xf /= xf[-1]
+    d, keep = make_desc(xf, inputs.uniform_faces(12), inputs.uniform_faces(8), (2, 2, 2), ra=1e6, pr=1.0,
+                        dt=1e-5, step_method="sweep", **kw)
+    with pytest.raises(_lib.MRError) as e:
+        host_z_system(d, 0)
+    assert e.value.status == _lib.MR_EINVAL
+
+
+def test_unknown_step_method_rejected():
+    assert _init_status(step_method=3) == _lib.MR_EINVAL
+    assert _init_status(step_method=-1) == _lib.MR_EINVAL
 
 
 def test_null_arguments_rejected():
