@@ -241,6 +241,21 @@ int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps,
 int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
                mr_nu* host_out, void* stream);
 
+/* mr_nusselt for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results (bit for bit) as mr_nusselt with host_out NULL, with
+ * the reduction partials in a fixed device array of the library (3.15 MB per
+ * GPU, set up by mr_init on its device and held until the process ends)
+ * instead of the context's lazily allocated buffer.  Allocates nothing.
+ * Limit: nz <= 1024 (MR_ESHAPE beyond).  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams, other threads, other
+ * contexts of the same device) race and must be serialised by the caller;
+ * each call rewrites every partial it reads, so nothing needs clearing between
+ * calls.  Asynchronous on the stream; no host summary (read dev_profile's last
+ * five values). */
+int mr_nusselt_noalloc(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
+                       void* stream);
+
 /* Dissipation Nusselt number (Sec. 4.1, Eq. 23): Nu_T = eps_T (Ra Pr)^(1/2) with
  * eps_T = kappa <|grad theta|^2>_V, the volume mean of the squared gradient
  * summed face by face: each face adds its squared difference quotient times

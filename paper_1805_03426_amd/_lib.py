@@ -23,6 +23,7 @@ EXPORTS = [
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
     "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
     "mr_coarse_step", "mr_host_z_face_weights", "mr_scalar_steps", "mr_get_step_method",
+    "mr_nusselt_noalloc",
 ]
 
 
@@ -87,6 +88,7 @@ def lib():
         "mr_velocity_grad": (c_int, [P, c_int32, POINTER(c_int64), POINTER(c_void_p),
                                      POINTER(c_void_p), P, P, P, P]),
         "mr_nusselt": (c_int, [P, P, P, P, POINTER(mr_nu), P]),
+        "mr_nusselt_noalloc": (c_int, [P, P, P, P, P]),
         "mr_copy_probe": (c_int, [P, P, c_int64, P]),
         "mr_thermal_dissipation": (c_int, [P, P, P, POINTER(c_double), P]),
         "mr_interpolate_velocity_time": (c_int, [P, P, P, P, P, P, P, c_int64, c_int64, P, P, P, P]),

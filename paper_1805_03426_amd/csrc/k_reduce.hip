@@ -7,10 +7,42 @@
 // are bitwise reproducible.  Nusselt sums are double-double (error-free
 // two-sum), i.e. compensated.
 #include <algorithm>
+#include <mutex>
 
 #include "mr_internal.h"
 
 namespace mr {
+
+// Fixed device memory for the Nusselt partials of the allocation-free entry
+// point: (nz + 1) faces x at most kNuMaxParts horizontal parts x 6 doubles,
+// for nz up to kNuMaxFaces (3.15 MB per GPU, held until the process ends).
+// In host code the array's name is only a stand-in: its device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr int kNuMaxParts = 64;
+constexpr size_t kNuScratchDoubles = (size_t)(1024 + 1) * kNuMaxParts * 6;
+static __device__ __align__(256) double scratch[kNuScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = (double*)ptr;
+  return hipSuccess;
+}
+
 namespace {
 
 __device__ __forceinline__ double shfl_down_d(double v, int off) {
@@ -221,7 +253,22 @@ __global__ void __launch_bounds__(256) copy_kernel(const int4* __restrict__ src,
 int nu_parts(const mr_ctx* c) {
   const int64_t nxy = (int64_t)c->nx * c->ny;
   int64_t P = (nxy + 256 * 16 - 1) / (256 * 16);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(P, 64));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(P, kNuMaxParts));
+}
+
+// The two Nusselt kernels with the partials in `part`.
+void nusselt_kernels(mr_ctx* c, const void* th, const void* w, double* prof, double* part, int P,
+                     hipStream_t s) {
+  const dim3 grid(P, (c->nz + 1 + kNuFaces - 1) / kNuFaces);
+  const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
+  if (c->precision == MR_FP64)
+    hipLaunchKernelGGL(nu_partial<double>, grid, dim3(256), 0, s, (const double*)th, (const double*)w,
+                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
+  else
+    hipLaunchKernelGGL(nu_partial<float>, grid, dim3(256), 0, s, (const float*)th, (const float*)w,
+                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
+  hipLaunchKernelGGL(nu_final, dim3(1), dim3(256), 0, s, (const double*)part, P, c->nz, c->dcz,
+                     c->hz64, c->atot, sqrt(c->ra * c->pr), prof);
 }
 
 }  // namespace
@@ -260,17 +307,27 @@ hipError_t launch_nusselt(mr_ctx* c, const void* th, const void* w, double* prof
   if (c->nz > kNuMaxFaces) return hipErrorInvalidValue;
   hipError_t e = ensure_red(c, sizeof(double) * part);
   if (e != hipSuccess) return e;
-  const dim3 grid(P, (c->nz + 1 + kNuFaces - 1) / kNuFaces);
-  const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
-  if (c->precision == MR_FP64)
-    hipLaunchKernelGGL(nu_partial<double>, grid, dim3(256), 0, s, (const double*)th, (const double*)w,
-                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, c->red);
-  else
-    hipLaunchKernelGGL(nu_partial<float>, grid, dim3(256), 0, s, (const float*)th, (const float*)w,
-                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, c->red);
-  hipLaunchKernelGGL(nu_final, dim3(1), dim3(256), 0, s, (const double*)c->red, P, c->nz, c->dcz,
-                     c->hz64, c->atot, sqrt(c->ra * c->pr), prof);
+  nusselt_kernels(c, th, w, prof, c->red, P, s);
   return hipGetLastError();
+}
+
+int nusselt_fixed(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s) {
+  const int P = nu_parts(c);
+  if (c->nz > kNuMaxFaces || (size_t)(c->nz + 1) * P * 6 > kNuScratchDoubles) return MR_ESHAPE;
+  if (c->device < 0 || c->device >= kMaxDevices) return MR_EINVAL;
+  double* part;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    part = g_scratch[c->device];
+  }
+  if (!part) return MR_EINVAL;   // mr_init sets it up for the context's device
+  nusselt_kernels(c, th, w, prof, part, P, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->last_err = (int)e;
+    return MR_EHIP;
+  }
+  return MR_OK;
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t nbytes, hipStream_t s) {

@@ -682,6 +682,9 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   }
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { int r = hip_fail(c, e); delete c; return r; }
+  // the allocation-free entry point's fixed memory on this device
+  e = mr::scratch_init(c->device);
+  if (e != hipSuccess) { int r = hip_fail(c, e); delete c; return r; }
   e = hipMalloc(&c->tables, pk.buf.size());
   if (e != hipSuccess) { delete c; (void)hipGetLastError(); return MR_ENOMEM; }
   e = hipMemcpy(c->tables, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
@@ -836,6 +839,12 @@ int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profil
       if (!std::isfinite(t)) return MR_ENONFINITE;
   }
   return MR_OK;
+}
+
+int mr_nusselt_noalloc(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
+                       void* stream) {
+  if (!ctx || !theta || !w || !dev_profile) return MR_EINVAL;
+  return mr::nusselt_fixed(ctx, theta, w, dev_profile, as_stream(stream));
 }
 
 int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, double* host_out,

@@ -164,6 +164,11 @@ hipError_t launch_sweep_steps(mr_ctx* c, int64_t n0, int count, const void* thp,
                               hipStream_t s);
 // Grows the context's reduction scratch to at least `bytes`.
 hipError_t ensure_red(mr_ctx* c, size_t bytes);
+// The fixed device memory of the allocation-free Nusselt entry point: looks up
+// its address on `device` (the current device) once per device.
+hipError_t scratch_init(int device);
+// mr_nusselt's kernels on that fixed memory (status code; allocates nothing).
+int nusselt_fixed(mr_ctx* c, const void* th, const void* w, double* prof, hipStream_t s);
 
 // Double-double (error-free two-sum) accumulation for compensated reductions.
 struct DD {
