@@ -111,10 +111,11 @@ struct GradArgs {
   int wx, wy;
 };
 
-// One thread per dense cell (i, j, k) owns the faces on its low side: x-face i,
-// y-face j and, for k >= 1, z-face k, and adds tau theta_f (mu_R/h_R - mu_L/h_L)
-// for every step, theta_f the step's face value (the mean of the two cells, or
-// the fourth-order value with ORD4).  The walls' z faces carry no advective
+// Velocity gradient: every dense cell (i, j, k) owns the faces on its low
+// side (x-face i, y-face j and, for k >= 1, z-face k) and adds
+// tau theta_f (mu_R/h_R - mu_L/h_L) for every step, theta_f the step's face
+// value (the mean of the two cells, or the fourth-order value).
+// Fourth-order faces: one thread per cell (grad_kernel).  The walls' z faces carry no advective
 // flux, so their gradient stays as it is; a side-wall face (x-face 0 or
 // y-face 0 of a walled axis) gets zero.
 template <typename T, bool ORD4>
@@ -168,6 +169,104 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
   if (k > 0) A.gw[row + i] += sw;
 }
 
+// Second-order faces: a wavefront owns 64 columns of one row and a segment of
+// ZS z levels.  For each step in turn it loads theta and mu on the segment's
+// levels (and the level below it) and adds every step's contribution to
+// per-level accumulators in registers; the loads of a step are independent of
+// each other, so they are all in flight together.  The column to the left
+// comes from the lane beside it (lane 0 loads it in the instruction where the
+// others re-read their own value) and the row below from the wavefront beside
+// it in the workgroup (cache).  gu, gv, gw are then updated once per level.
+constexpr int kGradRows = 4;   // wavefronts (rows of 64 columns) per workgroup
+
+template <typename T, int KM, int ZS>
+__global__ void __launch_bounds__(64 * kGradRows) grad_seg(GradArgs<T> A) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ntx = (nx + kWave - 1) / kWave, nty = (ny + kGradRows - 1) / kGradRows;
+  const int tile = blockIdx.x % (ntx * nty);
+  const int k0 = blockIdx.x / (ntx * nty) * ZS;
+  const int xt = tile % ntx, jt = tile / ntx;
+  const int i_raw = xt * kWave + lane, j_raw = jt * kGradRows + r;
+  const bool act = i_raw < nx && j_raw < ny;
+  const bool wx = A.wx, wy = A.wy;
+  // lanes and rows past a ragged end read valid cells and store nothing
+  const int i = i_raw % nx, j = j_raw % ny;
+  const int im = i == 0 ? (wx ? 0 : nx - 1) : i - 1;
+  const int jm = j == 0 ? (wy ? 0 : ny - 1) : j - 1;
+  const int nxy = nx * ny;
+  constexpr unsigned sz = sizeof(T);
+  const unsigned oc = (unsigned)(j * nx + i) * sz;
+  const unsigned oxe = lane == 0 ? (unsigned)(j * nx + im) * sz : oc;   // lane 0: its left column
+  const unsigned oym = (unsigned)(jm * nx + i) * sz;
+  const T half = T(0.5);
+  const T ihx = A.g.ihx[i], ihxm = A.g.ihx[im], ihy = A.g.ihy[j], ihym = A.g.ihy[jm];
+  auto at = [&](const T* f, int k, unsigned off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(f + (size_t)k * nxy) + off);
+  };
+  T ihz[ZS + 1];   // 1/hz of the level below the segment and of its levels
+#pragma unroll
+  for (int z = 0; z <= ZS; ++z) {
+    const int k = min(max(k0 + z - 1, 0), nz - 1);
+    ihz[z] = A.g.ihz[k];
+  }
+  T su[ZS], sv[ZS], sw[ZS];
+#pragma unroll
+  for (int z = 0; z < ZS; ++z) su[z] = sv[z] = sw[z] = T(0);
+#pragma unroll
+  for (int s = 0; s < KM; ++s) {
+    if (s < A.count) {
+      const T* th = A.th[s];
+      const T* mu = A.mu[s];
+      const T tau = A.tau[s];
+      // levels k0-1 .. k0+ZS-1 (clamped into the grid; the ones outside add nothing)
+      T tc[ZS + 1], mc[ZS + 1], te[ZS], me[ZS], ty[ZS], my[ZS];
+#pragma unroll
+      for (int z = 0; z <= ZS; ++z) {
+        const int k = min(max(k0 + z - 1, 0), nz - 1);
+        tc[z] = at(th, k, oc);
+        mc[z] = at(mu, k, oc);
+        if (z > 0) {
+          te[z - 1] = at(th, k, oxe);
+          me[z - 1] = at(mu, k, oxe);
+          ty[z - 1] = at(th, k, oym);
+          my[z - 1] = at(mu, k, oym);
+        }
+      }
+#pragma unroll
+      for (int z = 0; z < ZS; ++z) {
+        const T t = tc[z + 1], m = mc[z + 1];
+        const T tl = line::lane_shr(t), ml = line::lane_shr(m);
+        const T txm = lane == 0 ? te[z] : tl, mxm = lane == 0 ? me[z] : ml;
+        su[z] += tau * (half * (txm + t)) * (m * ihx - mxm * ihxm);
+        sv[z] += tau * (half * (ty[z] + t)) * (m * ihy - my[z] * ihym);
+        sw[z] += tau * (half * (tc[z] + t)) * (m * ihz[z + 1] - mc[z] * ihz[z]);
+      }
+    }
+  }
+  const bool zu = wx && i == 0, zv = wy && j == 0;   // side-wall faces: no gradient
+#pragma unroll
+  for (int z = 0; z < ZS; ++z) {
+    const int k = k0 + z;
+    if (act && k < nz) {
+      const size_t o = (size_t)k * nxy + (size_t)j * nx + i;
+      A.gu[o] += zu ? T(0) : su[z];
+      A.gv[o] += zv ? T(0) : sv[z];
+      if (k > 0) A.gw[o] += sw[z];   // the bottom wall face carries no flux
+    }
+  }
+}
+
+template <typename T, int KM>
+void launch_grad_seg(mr_ctx* c, const GradArgs<T>& a, hipStream_t s) {
+  constexpr int ZS = sizeof(T) == 8 ? 4 : 8;   // levels per segment
+  const int ntx = (c->nx + kWave - 1) / kWave, nty = (c->ny + kGradRows - 1) / kGradRows;
+  const int nseg = (c->nz + ZS - 1) / ZS;
+  const dim3 grid((unsigned)((int64_t)ntx * nty * nseg)), block(kWave * kGradRows);
+  hipLaunchKernelGGL((grad_seg<T, KM, ZS>), grid, block, 0, s, a);
+}
+
 template <typename T>
 hipError_t grad_t(mr_ctx* c, const Geom<T>& g, int count, const int64_t* steps,
                   const void* const* thetas, const void* const* mus, void* gu, void* gv, void* gw,
@@ -189,12 +288,17 @@ hipError_t grad_t(mr_ctx* c, const Geom<T>& g, int count, const int64_t* steps,
   a.nz = c->nz;
   a.wx = c->wx;
   a.wy = c->wy;
-  const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
-  const dim3 grid((unsigned)((cells + 255) / 256));
-  if (c->face_order == 4)
+  if (c->face_order == 4) {
+    const int64_t cells = (int64_t)c->nx * c->ny * c->nz;
+    const dim3 grid((unsigned)((cells + 255) / 256));
     hipLaunchKernelGGL((grad_kernel<T, true>), grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((grad_kernel<T, false>), grid, dim3(256), 0, s, a);
+  } else if (count <= 4) {
+    launch_grad_seg<T, 4>(c, a, s);
+  } else if (count <= 8) {
+    launch_grad_seg<T, 8>(c, a, s);
+  } else {
+    launch_grad_seg<T, kMaxGradSteps>(c, a, s);
+  }
   return hipGetLastError();
 }
 

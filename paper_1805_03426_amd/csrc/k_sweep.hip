@@ -299,7 +299,7 @@ using namespace sweep;
 // prefetch depths of 1 to 4: on one machine 16-row tiles took 5.75 ms (FP64)
 // and 3.01 ms (FP32) per step against 6.35 and 3.22 ms with 8 rows; two levels
 // ahead in FP64 (128 VGPRs) was 14% slower; bands of 8 were 2-5% faster than 4.
-constexpr int kSweepRows = 16;  // wavefronts (y rows) per workgroup
+constexpr int kSweepRows = kSweepTileRows;  // wavefronts (y rows) per workgroup
 constexpr int kSweepBand = 8;   // x tiles per band of the tile walk
 
 template <typename T>

@@ -18,6 +18,8 @@ enum StepKind { KIND_STARTUP = 0, KIND_LEAPFROG = 1, KIND_AVERAGE = 2, NKINDS = 
 constexpr int kMaxChunks = 16;
 constexpr int kChunkLens[] = {32, 36, 40};
 constexpr int kWave = 64;
+// rows of a column-sweep tile (64 x columns by this many y rows)
+constexpr int kSweepTileRows = 16;
 
 // Grid tables of one precision (device pointers into the context's table block).
 template <typename T>
