@@ -289,8 +289,10 @@ int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, co
 int mr_integrate_scalar(mr_ctx* ctx, const void* theta, void* theta_c, void* stream);
 
 /* One coarse step of the multiple-resolution loop for the scalar (Fig. 6):
- * for i = 1..mt, refine the coarse velocity at fraction i/mt into (u, v, w)
- * (as mr_interpolate_velocity_time) and take scalar step n0 + i - 1 (as
+ * for i = 1..mt, refine the coarse velocity at fraction (i-1)/mt into (u, v, w)
+ * (as mr_interpolate_velocity_time: the velocity at the start of sub-step i,
+ * the time level whose scalar the step advects, Eqs. 5-7) and take scalar
+ * step n0 + i - 1 (as
  * mr_scalar_step; the context's dt is the scalar step, i.e. the coarse step
  * divided by mt); then, if theta_c is not NULL, integrate the newest scalar
  * into theta_c (as mr_integrate_scalar).

@@ -62,14 +62,17 @@ def blend_velocity(U0, V0, W0, U1, V1, W1, i, mt):
 
 def coarse_step(g, p, n0, mt, th_prev, th_cur, U0, V0, W0, U1, V1, W1):
     """One coarse step of the multiple-resolution loop (Fig. 6) for the scalar:
-    for i = 1..M_t, interpolate the coarse velocity to fraction i/M_t (Eq. 21),
-    refine it to the dense grid (Sec. 3.2) and take scalar step n0 + i - 1
-    (Eqs. 6-7, with p.dt the scalar time step, i.e. the coarse step over M_t);
-    then integrate the newest scalar to the coarse grid (Eq. 20).
+    for i = 1..M_t, interpolate the coarse velocity to fraction (i-1)/M_t of the
+    coarse step (Eq. 21), refine it to the dense grid (Sec. 3.2) and take scalar
+    step n0 + i - 1 (Eqs. 6-7, with p.dt the scalar time step, i.e. the coarse
+    step over M_t); then integrate the newest scalar to the coarse grid (Eq. 20).
+    Sub-step i advances the scalar from time level n0 + i - 1, and the
+    advection C(theta^n) of Eqs. 5-7 is taken at level n, so its velocity is the
+    one at the start of the sub-step: fractions 0, 1/M_t, ..., (M_t-1)/M_t.
     Returns (theta^{n0+mt-1}, theta^{n0+mt}, Tc)."""
     prev, cur = th_prev, th_cur
     for i in range(1, mt + 1):
-        U, V, W = blend_velocity(U0, V0, W0, U1, V1, W1, i, mt)
+        U, V, W = blend_velocity(U0, V0, W0, U1, V1, W1, i - 1, mt)
         u, v, w = refine_velocity(g, U, V, W)
         nxt = scalar_step(g, p, n0 + i - 1, prev, cur, u, v, w)
         prev, cur = cur, nxt

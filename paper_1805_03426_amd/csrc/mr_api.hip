@@ -899,10 +899,11 @@ int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const vo
   hipStream_t s = as_stream(stream);
   if (ctx->sweep_pref) {
     // column sweeps: the kernel of sub-step i finishes theta^{n0+i-1} and
-    // starts sub-step i on the velocity refined just before it
+    // starts sub-step i on the velocity refined just before it (the velocity
+    // at the start of the sub-step, fraction (i-1)/mt)
     const int c0 = c;
     for (int32_t i = 1; i <= mt; ++i) {
-      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
+      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)(i - 1) / (double)mt, u, v, w, s));
       const int q = i - 1;
       int o = 0;
       while (o == c || o == p) ++o;
@@ -921,7 +922,7 @@ int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const vo
     c = o;
   } else {
     for (int32_t i = 1; i <= mt; ++i) {
-      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w, s));
+      MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)(i - 1) / (double)mt, u, v, w, s));
       const int64_t n = n0 + i - 1;
       int o = 0;
       while (o == c || o == p) ++o;   // the buffer holding neither level
