@@ -22,9 +22,10 @@ FP32_TOL = 1e-5
 # differs from the oracle by a few units of FP32 rounding of theta (the cast
 # inputs and the stored result), about 1e-7 absolute; the fluctuation (rms
 # 0.02) and the increment (about 5e-3 per step here) turn that into relative
-# errors near 5e-6 and 2e-5.
+# errors of order 1e-6 and 1e-5.  Measured worst over the FP32 parity cases:
+# fluctuation 1.9e-6, increment 3.1e-5; the bounds are 5x and 10x those.
 FP32_FLUCT_TOL = 1e-5
-FP32_INCR_TOL = 1e-3
+FP32_INCR_TOL = 3e-4
 EPS = np.finfo(np.float64).eps
 
 
