@@ -45,6 +45,13 @@ struct RefArgs {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// A wave-uniform table value, read through the constant address space (a
+// scalar load that does not wait behind the vector loads in flight).
+template <typename T>
+__device__ __forceinline__ T tab(const T* p, int k) {
+  return ((const __attribute__((address_space(4))) T*)(p))[k];
+}
+
 template <typename T>
 __device__ __forceinline__ T rdot(const T* R, const T q[3]) {
   return R[0] * q[0] + R[1] * q[1] + R[2] * q[2];
@@ -525,6 +532,426 @@ __global__ void __launch_bounds__(256) tx_split(RefArgs<T> A) {
         gather<T>(A.g.Rx, A.g.sx, ncx, mx, !A.wx, I, [&](int i) { return gv[k * nxy + j * nx + i]; });
 }
 
+// X^T in one kernel: a workgroup owns one dense row j and a range of levels;
+// per level it stages the row of gu (and of the row below, and keeps the level
+// below's) in LDS, forms the march adjoints gv_tot and gw_tot of every dense
+// column there (as tx_march), and gathers them into the coarse columns with
+// R^T (as tx_split), so that the two dense intermediates never go to memory.
+// The rows j and j - 1 of one level are read by neighbouring workgroups of the
+// same XCD at nearly the same time.
+constexpr size_t kFuseMaxLds = 64 * 1024;   // LDS budget of the fused refinement kernels
+constexpr int kRowCells = 1;      // coarse cells per thread of tx_row
+constexpr int kRowThreads = 512;  // most threads of a tx_row workgroup (rows up to 512 coarse cells)
+
+// R^T gather of coarse column c on a periodic axis: the cells whose stencils
+// hold c are c-1, c, c+1, at stencil positions 2, 1, 0; their R entries are
+// level-invariant, so a thread loads them once (rc) and gathers every level
+// from the dense values in LDS.
+template <typename T, int MX>
+struct RowGather {
+  T rc[3][MX];
+  int base[3];   // first dense column of cells c-1, c, c+1
+  __device__ void init(const RefArgs<T>& A, int c) {
+    const int cs[3] = {wrap(c - 1, A.ncx), c, wrap(c + 1, A.ncx)};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      base[q] = cs[q] * MX;
+#pragma unroll
+      for (int p = 0; p < MX; ++p) rc[q][p] = A.g.Rx[(cs[q] * MX + p) * 3 + (2 - q)];
+    }
+  }
+  __device__ T operator()(const T* val) const {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int p = 0; p < MX; ++p) acc += rc[q][p] * val[base[q] + p];
+    return acc;
+  }
+};
+
+template <typename T, int MX>
+__device__ __forceinline__ T gather_row(const RefArgs<T>& A, const RowGather<T, MX>& G, const T* val, int c) {
+  if (MX == 1) return val[c];
+  if (!A.wx) return G(val);
+  // walled axis: the general search (one-sided stencils next to the walls)
+  return gather<T>(A.g.Rx, A.g.sx, A.ncx, MX, false, c, [&](int i) { return val[i]; });
+}
+
+// X^T in one kernel: a workgroup owns one dense row j and a range of levels,
+// a thread whole coarse cells of the row.  Per level each thread forms the
+// march adjoints of its cells' dense columns from its own gu values (this
+// level, the row below, and the level below, carried) as tx_march does,
+// writes them to LDS, and after one barrier gathers its coarse columns with
+// R^T from its own and the neighbouring cells (as tx_split), so that the two
+// dense intermediates never go to memory.  Loads run one level ahead; the LDS
+// rows alternate by level parity (one barrier per level).
+template <typename T, int MX>
+__global__ void __launch_bounds__(kRowThreads) tx_row(RefArgs<T> A, int kc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* const sm = reinterpret_cast<T*>(smem_raw);
+  const int nx = A.nx, ny = A.ny, nz = A.nz, ncx = A.ncx;
+  const int nxy = nx * ny, nyx = ny * ncx;
+  T* const gvt[2] = {sm, sm + nx};            // gv_tot of a level, by parity
+  T* const gwt[2] = {sm + 2 * nx, sm + 3 * nx};  // gw_tot on a level's bottom face
+  T* const gwn = sm + 4 * nx;                 // gw_tot on the top face (last level)
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int j = b % ny, chunk = b / ny;
+  const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
+  const int jm = wrap(j - 1, ny);
+  const bool zjm = A.wy && j == 0;
+  const T ihy = A.g.ihy[j], ihym = A.g.ihy[jm];
+  const T* gu = A.in0;
+  const T* gv = A.in1;
+  const T* gw = A.in2;
+  const int t = threadIdx.x, nt = blockDim.x;
+  struct Lvl {
+    T a[kRowCells][MX], bm[kRowCells][MX], v[kRowCells][MX], w[kRowCells][MX];
+  };
+  auto fetch = [&](int k, Lvl& L) {
+    const size_t lv = (size_t)min(k, nz - 1) * nxy;
+#pragma unroll
+    for (int c = 0; c < kRowCells; ++c) {
+      const int I = t + c * nt;
+      if (I < ncx) {
+#pragma unroll
+        for (int p = 0; p < MX; ++p) {
+          const int i = I * MX + p;
+          L.a[c][p] = gu[lv + j * nx + i];
+          L.bm[c][p] = gu[lv + jm * nx + i];
+          L.v[c][p] = gv[lv + j * nx + i];
+          L.w[c][p] = gw[lv + j * nx + i];
+        }
+      }
+    }
+  };
+  // level-invariant per-thread values: R entries of the gather, widths
+  RowGather<T, MX> G[kRowCells];
+  T hx[kRowCells][MX];
+#pragma unroll
+  for (int c = 0; c < kRowCells; ++c) {
+    const int I = min(t + c * nt, ncx - 1);
+    G[c].init(A, I);
+#pragma unroll
+    for (int p = 0; p < MX; ++p) hx[c][p] = A.g.hx[I * MX + p];
+  }
+  // suffix sums of gu on the level below (for the bottom faces' adjoint)
+  T sprev[kRowCells][MX];
+#pragma unroll
+  for (int c = 0; c < kRowCells; ++c) {
+    const int I = t + c * nt;
+#pragma unroll
+    for (int p = 0; p < MX; ++p) sprev[c][p] = T(0);
+    if (k0 > 0 && I < ncx) {
+      const size_t lv = (size_t)(k0 - 1) * nxy + j * nx + I * MX;
+#pragma unroll
+      for (int p = 0; p < MX; ++p)
+        sprev[c][p] = suffix<T>(0, MX, p, [&](int q) { return gu[lv + q]; });
+    }
+  }
+  Lvl cur, nxt;
+  fetch(k0, cur);
+  for (int k = k0; k < k1; ++k) {
+    if (k + 1 < k1) fetch(k + 1, nxt);
+    T* const vt = gvt[k & 1];
+    T* const wt = gwt[k & 1];
+    const T ihz = tab(A.g.ihz, k);
+    const T ihzm = k > 0 ? tab(A.g.ihz, k - 1) : T(0);
+    const size_t orow = (size_t)k * nyx + j * ncx;
+#pragma unroll
+    for (int c = 0; c < kRowCells; ++c) {
+      const int I = t + c * nt;
+      if (I < ncx) {
+        T tot = T(0);
+#pragma unroll
+        for (int p = 0; p < MX; ++p) {
+          const int i = I * MX + p;
+          const T hxi = hx[c][p];
+          const T su = suffix<T>(0, MX, p, [&](int q) { return cur.a[c][q]; });
+          const T c0 = -su;
+          const T cjm = zjm ? T(0) : -suffix<T>(0, MX, p, [&](int q) { return cur.bm[c][q]; });
+          const T ckm = k > 0 ? -sprev[c][p] : T(0);
+          vt[i] = cur.v[c][p] + cjm * hxi * ihym - c0 * hxi * ihy;
+          wt[i] = cur.w[c][p] + ckm * hxi * ihzm - c0 * hxi * ihz;
+          if (k == nz - 1) gwn[i] = gw[(size_t)nz * nxy + j * nx + i] + c0 * hxi * ihz;
+          sprev[c][p] = su;
+          tot += cur.a[c][p];
+        }
+        A.out0[orow + I] = tot;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kRowCells; ++c) {
+      const int I = t + c * nt;
+      if (I < ncx) {
+        A.out1[orow + I] = gather_row<T, MX>(A, G[c], vt, I);
+        A.out2[orow + I] = gather_row<T, MX>(A, G[c], wt, I);
+        if (k == nz - 1) A.out2[(size_t)nz * nyx + j * ncx + I] = gather_row<T, MX>(A, G[c], gwn, I);
+      }
+    }
+    cur = nxt;
+  }
+}
+
+template <typename T>
+bool launch_tx_row(mr_ctx* c, const RefArgs<T>& a, hipStream_t s) {
+  const size_t lds = sizeof(T) * 5 * (size_t)c->nx;
+  if (lds > kFuseMaxLds || c->ncx > kRowCells * kRowThreads || c->mx > 4) return false;
+  // levels per workgroup: about 16 workgroups per CU in all, at least 4 levels each
+  const int64_t want = 256 * 16;
+  int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(c->nz / 4, (want + c->ny - 1) / c->ny));
+  const int kc = (c->nz + nchunk - 1) / nchunk;
+  nchunk = (c->nz + kc - 1) / kc;
+  const int threads = (c->ncx + kRowCells * kWave - 1) / (kRowCells * kWave) * kWave;
+  const dim3 grid((unsigned)((int64_t)c->ny * nchunk)), block(threads);
+  switch (c->mx) {
+    case 1: hipLaunchKernelGGL((tx_row<T, 1>), grid, block, lds, s, a, kc); break;
+    case 2: hipLaunchKernelGGL((tx_row<T, 2>), grid, block, lds, s, a, kc); break;
+    case 3: hipLaunchKernelGGL((tx_row<T, 3>), grid, block, lds, s, a, kc); break;
+    default: hipLaunchKernelGGL((tx_row<T, 4>), grid, block, lds, s, a, kc); break;
+  }
+  return true;
+}
+
+// Y^T in one kernel: a thread owns coarse column I on dense level k (cells k
+// and bottom face k) and walks a range of coarse rows J.  Per row it forms the
+// march adjoints of the row's dense y rows from gV_zy (its own column, the
+// column I - 1 from the lane beside it, the level below from memory) as
+// ty_march does, keeps them for the last five rows, and gathers every row
+// whose R^T sources are complete (R_y stencils reach two rows at a wall), as
+// ty_split does.  The per-row R_y entries are wave-uniform (scalar loads).
+constexpr int kYRows = 32;   // coarse rows per thread (plus two halo rows each side)
+
+template <typename T, int MY>
+__global__ void __launch_bounds__(256) ty_fused(RefArgs<T> A, int nrowc) {
+  const int ncx = A.ncx, ncy = A.ncy, nz = A.nz, ny = A.ny;
+  const int ncxy = ncx * ncy, nyx = ny * ncx;
+  const int lane = threadIdx.x;
+  const int ntx = (ncx + kWave - 1) / kWave;
+  const int bid = blockIdx.x;
+  const int xt = bid % ntx;
+  const int k = (bid / ntx) % (nz + 1);             // cell level k (< nz) and face k
+  const int rc = bid / (ntx * (nz + 1));            // range of output rows
+  const int I_raw = xt * kWave + lane;
+  const bool act = I_raw < ncx;
+  const int I = min(I_raw, ncx - 1);
+  const int Im = wrap(I - 1, ncx);
+  const bool zim = A.wx && I == 0;
+  const int J0 = rc * nrowc, J1 = min(ncy, J0 + nrowc);
+  const bool cells = k < nz;   // the top face has no cell level of its own
+  const T iHX = A.g.iHX[I], iHXm = A.g.iHX[Im];
+  const T ihz = cells ? tab(A.g.ihz, k) : T(0);
+  const T ihzm = k > 0 ? tab(A.g.ihz, k - 1) : T(0);
+  const T* gUzy = A.in0;
+  const T* gVzy = A.in1;
+  const T* gWzy = A.in2;
+  auto at = [&](const T* f, int kk, int j, int i) { return f[(size_t)kk * nyx + (size_t)j * ncx + i]; };
+  // march adjoints of the last five coarse rows (window slot d holds row J - 4 + d)
+  T wu[5][MY], ww[5][MY];
+#pragma unroll
+  for (int d = 0; d < 5; ++d)
+#pragma unroll
+    for (int q = 0; q < MY; ++q) wu[d][q] = ww[d][q] = T(0);
+  // the output row Jo gathers from rows Jo-2 .. Jo+2 (window slots 0 .. 4)
+  auto emit = [&](int Jo) {
+    T au = T(0), aw = T(0);
+    if (MY == 1) {   // R = [0 1 0]: the row itself
+      au = wu[2][0];
+      aw = ww[2][0];
+    }
+#pragma unroll
+    for (int d = 0; d < 5 && MY > 1; ++d) {
+      const int J = Jo - 2 + d;
+      const int Jw = A.wy ? J : wrapm(J, ncy);
+      if (A.wy && (J < 0 || J >= ncy)) continue;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (tab(A.g.sy, Jw * 3 + r) != Jo) continue;
+        if (!A.wy && (J - Jo < -1 || J - Jo > 1)) continue;   // periodic: J - 1 .. J + 1 only
+#pragma unroll
+        for (int q = 0; q < MY; ++q) {
+          const T R = tab(A.g.Ry, (Jw * MY + q) * 3 + r);
+          au += R * wu[d][q];
+          aw += R * ww[d][q];
+        }
+      }
+    }
+    if (act) {
+      if (cells) A.out0[(size_t)k * ncxy + Jo * ncx + I] = au;
+      A.out2[(size_t)k * ncxy + Jo * ncx + I] = aw;
+    }
+  };
+  const int Ja = max(J0 - 2, A.wy ? 0 : J0 - 2), Jb = min(J1 + 2, A.wy ? ncy : J1 + 2);
+  for (int Ju = Ja; Ju < Jb; ++Ju) {
+    const int J = wrapm(Ju, ncy);
+    // shift the window
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int q = 0; q < MY; ++q) {
+        wu[d][q] = wu[d + 1][q];
+        ww[d][q] = ww[d + 1][q];
+      }
+    T vc[MY], vl[MY], vb[MY];
+#pragma unroll
+    for (int q = 0; q < MY; ++q) {
+      const int j = J * MY + q;
+      vc[q] = cells ? at(gVzy, k, j, I) : T(0);
+      vl[q] = cells ? at(gVzy, k, j, Im) : T(0);   // the lane beside it loads the same line
+      vb[q] = k > 0 ? at(gVzy, k - 1, j, I) : T(0);
+    }
+    T tot = T(0);
+#pragma unroll
+    for (int q = 0; q < MY; ++q) {
+      const int j = J * MY + q;
+      const T hy = A.g.hy[j];
+      T s0 = T(0), sl = T(0), sb = T(0);
+#pragma unroll
+      for (int qq = q + 1; qq < MY; ++qq) {
+        s0 += vc[qq];
+        sl += vl[qq];
+        sb += vb[qq];
+      }
+      const T c0 = -s0, cim = zim ? T(0) : -sl, ckm = k > 0 ? -sb : T(0);
+      wu[4][q] = cells ? at(gUzy, k, j, I) + cim * hy * iHXm - c0 * hy * iHX : T(0);
+      T wv = at(gWzy, k, j, I) + ckm * hy * ihzm;
+      if (cells) wv -= c0 * hy * ihz;
+      ww[4][q] = wv;
+      tot += vc[q];
+    }
+    if (cells && act && Ju >= J0 && Ju < J1) A.out3[(size_t)k * ncxy + J * ncx + I] = tot;
+    // the row two back now has every source row in the window
+    const int Jo = Ju - 2;
+    if (Jo >= J0 && Jo < J1) emit(Jo);
+  }
+  // rows whose later sources lie beyond a wall
+  for (int Jo = max(J0, Jb - 2); Jo < J1; ++Jo) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int q = 0; q < MY; ++q) {
+        wu[d][q] = wu[d + 1][q];
+        ww[d][q] = ww[d + 1][q];
+      }
+#pragma unroll
+    for (int q = 0; q < MY; ++q) wu[4][q] = ww[4][q] = T(0);
+    emit(Jo);
+  }
+}
+
+// Z^T in one kernel: a thread owns coarse column (I, J) and walks a range of
+// coarse layers K.  Per layer it forms the march adjoints of the layer's dense
+// levels from gW_z (its own column, the columns I - 1 and J - 1) as tz_march
+// does, writes gW, keeps the adjoints of the last five layers, and gathers
+// every layer whose R_z^T sources are complete (R_z stencils reach two layers
+// at a wall), as tz_split does.  The per-layer R_z entries are wave-uniform.
+constexpr int kZLayers = 16;   // coarse layers per thread (plus two halo layers each side)
+
+template <typename T, int MZ>
+__global__ void __launch_bounds__(256) tz_fused(RefArgs<T> A, int nlayc) {
+  const int ncx = A.ncx, ncy = A.ncy, ncz = A.ncz, nz = A.nz;
+  const int ncxy = ncx * ncy;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = threadIdx.x / kWave;                 // 4 rows J per workgroup
+  const int ntx = (ncx + kWave - 1) / kWave, nty = (ncy + 3) / 4;
+  const int bid = blockIdx.x;
+  const int xt = bid % ntx, yt = (bid / ntx) % nty, lc = bid / (ntx * nty);
+  const int I_raw = xt * kWave + lane, J_raw = yt * 4 + row;
+  const bool act = I_raw < ncx && J_raw < ncy;
+  const int I = min(I_raw, ncx - 1), J = min(J_raw, ncy - 1);
+  const int Im = wrap(I - 1, ncx), Jm = wrap(J - 1, ncy);
+  const bool zim = A.wx && I == 0, zjm = A.wy && J == 0;
+  const T iHX = A.g.iHX[I], iHXm = A.g.iHX[Im], iHY = A.g.iHY[J], iHYm = A.g.iHY[Jm];
+  const int K0 = lc * nlayc, K1 = min(ncz, K0 + nlayc);
+  const T* gUz = A.in0;
+  const T* gVz = A.in1;
+  const T* gWz = A.in2;
+  auto at = [&](const T* f, int k, int j, int i) { return f[(size_t)k * ncxy + (size_t)j * ncx + i]; };
+  T wu[5][MZ], wv[5][MZ];   // window slot d holds layer K - 4 + d
+#pragma unroll
+  for (int d = 0; d < 5; ++d)
+#pragma unroll
+    for (int p = 0; p < MZ; ++p) wu[d][p] = wv[d][p] = T(0);
+  auto emit = [&](int Ko) {
+    T au = T(0), av = T(0);
+    if (MZ == 1) {   // R = [0 1 0]: the layer itself
+      au = wu[2][0];
+      av = wv[2][0];
+    }
+#pragma unroll
+    for (int d = 0; d < 5 && MZ > 1; ++d) {
+      const int K = Ko - 2 + d;
+      if (K < 0 || K >= ncz) continue;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (tab(A.g.sz, K * 3 + r) != Ko) continue;
+#pragma unroll
+        for (int p = 0; p < MZ; ++p) {
+          const T R = tab(A.g.Rz, (K * MZ + p) * 3 + r);
+          au += R * wu[d][p];
+          av += R * wv[d][p];
+        }
+      }
+    }
+    if (act) {
+      // a low wall face is taken as zero by the forward map: its gradient is zero
+      A.out0[(size_t)Ko * ncxy + J * ncx + I] = zim ? T(0) : au;
+      A.out1[(size_t)Ko * ncxy + J * ncx + I] = zjm ? T(0) : av;
+    }
+  };
+  auto shift = [&]() {
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int p = 0; p < MZ; ++p) {
+        wu[d][p] = wu[d + 1][p];
+        wv[d][p] = wv[d + 1][p];
+      }
+  };
+  const int Ka = max(K0 - 2, 0), Kb = min(K1 + 2, ncz);
+  for (int K = Ka; K < Kb; ++K) {
+    shift();
+    T wc[MZ], wl[MZ], wb[MZ];
+#pragma unroll
+    for (int p = 0; p < MZ; ++p) {
+      const int k = K * MZ + p;
+      wc[p] = at(gWz, k, J, I);
+      wl[p] = at(gWz, k, J, Im);   // the lane beside it loads the same line
+      wb[p] = at(gWz, k, Jm, I);
+    }
+    T tot = T(0);
+#pragma unroll
+    for (int p = 0; p < MZ; ++p) {
+      const int k = K * MZ + p;
+      const T hz = tab(A.g.hz, k);
+      T s0 = T(0), sl = T(0), sb = T(0);
+#pragma unroll
+      for (int q = p + 1; q < MZ; ++q) {
+        s0 += wc[q];
+        sl += wl[q];
+        sb += wb[q];
+      }
+      const T c0 = -s0, cim = zim ? T(0) : -sl, cjm = zjm ? T(0) : -sb;
+      wu[4][p] = at(gUz, k, J, I) + cim * hz * iHXm - c0 * hz * iHX;
+      wv[4][p] = at(gVz, k, J, I) + cjm * hz * iHYm - c0 * hz * iHY;
+      tot += wc[p];
+    }
+    if (act && K >= K0 && K < K1) {
+      A.out2[(size_t)K * ncxy + J * ncx + I] = tot;
+      if (K == ncz - 1) A.out2[(size_t)ncz * ncxy + J * ncx + I] = at(gWz, nz, J, I);
+    }
+    const int Ko = K - 2;
+    if (Ko >= K0 && Ko < K1) emit(Ko);
+  }
+  for (int Ko = max(K0, Kb - 2); Ko < K1; ++Ko) {
+    shift();
+#pragma unroll
+    for (int p = 0; p < MZ; ++p) wu[4][p] = wv[4][p] = T(0);
+    emit(Ko);
+  }
+}
+
 // Y1: thread per (coarse I, coarse J, dense k).  in1 = gVzy; out0 = gUzy (+=),
 // out2 = gWzy (+=), out3 = gVz.
 template <typename T>
@@ -646,7 +1073,6 @@ hipError_t ensure(void** buf, size_t* have, size_t need) {
 constexpr int kFusedRows = 6;       // most coarse rows per tile
 constexpr int kFusedWgs = 8192;     // workgroups the layer split aims for
 constexpr int kFusedMinKc = 4;      // fewest coarse layers per workgroup
-constexpr size_t kFuseMaxLds = 64 * 1024;
 
 // LDS bytes of refine_fused for a tile of TI x TJ coarse cells.
 template <typename T>
@@ -734,43 +1160,83 @@ hipError_t refine_transpose_t(mr_ctx* c, const Geom<T>& g, const void* gu, const
   const int64_t d0 = (int64_t)c->nz * c->ny * c->nx, d1 = (int64_t)(c->nz + 1) * c->ny * c->nx;
   const int64_t zc = (int64_t)c->nz * c->ncy * c->ncx, zc1 = (int64_t)(c->nz + 1) * c->ncy * c->ncx;
   const int64_t yc = (int64_t)c->nz * c->ny * c->ncx, yc1 = (int64_t)(c->nz + 1) * c->ny * c->ncx;
-  const size_t need = sizeof(T) * (size_t)(d0 + d1 + 2 * yc + yc1 + 2 * zc + zc1);
+  // stage x transposed in one kernel where a dense row fits (up to 512 coarse
+  // cells of at most 4 columns, five dense rows within the LDS budget);
+  // otherwise through two dense intermediates
+  const bool fused_x = sizeof(T) * 5 * (size_t)c->nx <= kFuseMaxLds && c->ncx <= kRowCells * kRowThreads &&
+                       c->mx <= 4;
+  const size_t need = sizeof(T) * (size_t)((fused_x ? 0 : d0 + d1) + 2 * yc + yc1 + 2 * zc + zc1);
   hipError_t e = ensure(&c->interp_bwd_tmp, &c->interp_bwd_tmp_bytes, need);
   if (e != hipSuccess) return e;
   T* gv_tot = (T*)c->interp_bwd_tmp;
   T* gw_tot = gv_tot + d0;
-  T* gUzy = gw_tot + d1;
+  T* gUzy = fused_x ? (T*)c->interp_bwd_tmp : gw_tot + d1;
   T* gVzy = gUzy + yc;
   T* gWzy = gVzy + yc;
   T* gUz = gWzy + yc1;
   T* gVz = gUz + zc;
   T* gWz = gVz + zc;
   RefArgs<T> a = ref_args<T>(c, g);
-  // stage x transposed
   a.in0 = (const T*)gu; a.in1 = (const T*)gv; a.in2 = (const T*)gw;
-  a.out0 = gUzy; a.out1 = gv_tot; a.out2 = gw_tot;
-  hipLaunchKernelGGL(tx_march<T>, dim3(nblk(yc)), dim3(256), 0, s, a);
-  a.in1 = gv_tot; a.in2 = gw_tot;
-  a.out1 = gVzy; a.out2 = gWzy;
-  hipLaunchKernelGGL(tx_split<T>, dim3(nblk(yc1)), dim3(256), 0, s, a);
-  // stage y transposed
+  a.out0 = gUzy;
+  if (fused_x) {
+    a.out1 = gVzy; a.out2 = gWzy;
+    launch_tx_row<T>(c, a, s);
+  } else {
+    a.out1 = gv_tot; a.out2 = gw_tot;
+    hipLaunchKernelGGL(tx_march<T>, dim3(nblk(yc)), dim3(256), 0, s, a);
+    a.in1 = gv_tot; a.in2 = gw_tot;
+    a.out1 = gVzy; a.out2 = gWzy;
+    hipLaunchKernelGGL(tx_split<T>, dim3(nblk(yc1)), dim3(256), 0, s, a);
+  }
+  // stage y transposed: one kernel for refinement factors up to 4
   a = ref_args<T>(c, g);
-  a.in1 = gVzy;
-  a.out0 = gUzy; a.out2 = gWzy; a.out3 = gVz;
-  hipLaunchKernelGGL(ty_march<T>, dim3(nblk(zc)), dim3(256), 0, s, a);
+  if (c->my <= 4) {
+    a.in0 = gUzy; a.in1 = gVzy; a.in2 = gWzy;
+    a.out0 = gUz; a.out2 = gWz; a.out3 = gVz;
+    const int nrc = (c->ncy + kYRows - 1) / kYRows;
+    const int nrowc = (c->ncy + nrc - 1) / nrc;
+    const int ntx = (c->ncx + kWave - 1) / kWave;
+    const dim3 grid((unsigned)((int64_t)ntx * (c->nz + 1) * ((c->ncy + nrowc - 1) / nrowc))), block(kWave);
+    switch (c->my) {
+      case 1: hipLaunchKernelGGL((ty_fused<T, 1>), grid, block, 0, s, a, nrowc); break;
+      case 2: hipLaunchKernelGGL((ty_fused<T, 2>), grid, block, 0, s, a, nrowc); break;
+      case 3: hipLaunchKernelGGL((ty_fused<T, 3>), grid, block, 0, s, a, nrowc); break;
+      default: hipLaunchKernelGGL((ty_fused<T, 4>), grid, block, 0, s, a, nrowc); break;
+    }
+  } else {
+    a.in1 = gVzy;
+    a.out0 = gUzy; a.out2 = gWzy; a.out3 = gVz;
+    hipLaunchKernelGGL(ty_march<T>, dim3(nblk(zc)), dim3(256), 0, s, a);
+    a = ref_args<T>(c, g);
+    a.in0 = gUzy; a.in2 = gWzy;
+    a.out0 = gUz; a.out2 = gWz;
+    hipLaunchKernelGGL(ty_split<T>, dim3(nblk(zc1)), dim3(256), 0, s, a);
+  }
+  // stage z transposed: one kernel for refinement factors up to 4
   a = ref_args<T>(c, g);
-  a.in0 = gUzy; a.in2 = gWzy;
-  a.out0 = gUz; a.out2 = gWz;
-  hipLaunchKernelGGL(ty_split<T>, dim3(nblk(zc1)), dim3(256), 0, s, a);
-  // stage z transposed
-  a = ref_args<T>(c, g);
-  a.in2 = gWz;
-  a.out0 = gUz; a.out1 = gVz; a.out2 = (T*)gW;
-  hipLaunchKernelGGL(tz_march<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
-  a = ref_args<T>(c, g);
-  a.in0 = gUz; a.in1 = gVz;
-  a.out0 = (T*)gU; a.out1 = (T*)gV;
-  hipLaunchKernelGGL(tz_split<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+  if (c->mz <= 4) {
+    a.in0 = gUz; a.in1 = gVz; a.in2 = gWz;
+    a.out0 = (T*)gU; a.out1 = (T*)gV; a.out2 = (T*)gW;
+    const int nlc = (c->ncz + kZLayers - 1) / kZLayers;
+    const int nlayc = (c->ncz + nlc - 1) / nlc;
+    const int ntx = (c->ncx + kWave - 1) / kWave, nty = (c->ncy + 3) / 4;
+    const dim3 grid((unsigned)((int64_t)ntx * nty * ((c->ncz + nlayc - 1) / nlayc))), block(256);
+    switch (c->mz) {
+      case 1: hipLaunchKernelGGL((tz_fused<T, 1>), grid, block, 0, s, a, nlayc); break;
+      case 2: hipLaunchKernelGGL((tz_fused<T, 2>), grid, block, 0, s, a, nlayc); break;
+      case 3: hipLaunchKernelGGL((tz_fused<T, 3>), grid, block, 0, s, a, nlayc); break;
+      default: hipLaunchKernelGGL((tz_fused<T, 4>), grid, block, 0, s, a, nlayc); break;
+    }
+  } else {
+    a.in2 = gWz;
+    a.out0 = gUz; a.out1 = gVz; a.out2 = (T*)gW;
+    hipLaunchKernelGGL(tz_march<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+    a = ref_args<T>(c, g);
+    a.in0 = gUz; a.in1 = gVz;
+    a.out0 = (T*)gU; a.out1 = (T*)gV;
+    hipLaunchKernelGGL(tz_split<T>, dim3(nblk((int64_t)c->ncx * c->ncy * c->ncz)), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

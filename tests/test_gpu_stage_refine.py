@@ -116,3 +116,63 @@ def test_stage_refine_transpose_parity(nc, m, gamma, prec):
             lhs = sum(np.vdot(a, b) for a, b in zip(Px, ys))
             rhs = sum(np.vdot(a, b) for a, b in zip(xs, PTy))
             assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,nc", [("fp64", (700, 3, 4)), ("fp32", (1400, 3, 3)), ("fp64", (40, 7, 5))])
+def test_transpose_wide_and_narrow_rows(prec, nc):
+    """The transposed refinement's x stage takes a whole dense row per level in
+    LDS for rows of up to 1024 columns (here 80); rows of 1400 (FP64) and 2800
+    (FP32) columns go through the two-kernel form.  Both against the oracle's
+    transpose."""
+    print("case transpose rows", prec, nc, flush=True)
+    case = Case(nc, (2, 2, 2), 1.5, kmax=1, precision=prec, random_velocity=True, dt=1e-6)
+    g = case.g
+    rng = np.random.default_rng(32)
+    dense = ((g.z.n, g.y.n, g.x.n), (g.z.n, g.y.n, g.x.n), (g.z.n + 1, g.y.n, g.x.n))
+    ys = [rng.standard_normal(s) for s in dense]
+    if prec == "fp32":
+        ys = [y.astype(np.float32).astype(np.float64) for y in ys]
+    want = O.refine_velocity_transpose(g, *ys)
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    with case.ctx() as ctx:
+        got = [host(t) for t in ctx.interpolate_velocity_backward(*[case.d(y) for y in ys])]
+    for a, b in zip(got, want):
+        assert rel_max(a, b) <= tol
+
+
+@pytest.mark.parametrize("side_y,m", [("periodic", (2, 2, 2)), ("walls", (2, 3, 2)), ("periodic", (3, 1, 1)),
+                                      ("walls", (1, 2, 3))])
+def test_transpose_row_and_layer_ranges(side_y, m):
+    """The fused y and z stages of the transposed refinement split the coarse
+    rows into ranges of up to 32 and the coarse layers into ranges of up to
+    16, each with two halo rows or layers on either side: 70 coarse rows and 40
+    coarse layers cross several range boundaries, on periodic and walled y
+    (one-sided stencils reach two rows), against the oracle's transpose."""
+    print("case transpose ranges", side_y, m, flush=True)
+    from paper_1805_03426_amd.context import Context
+    nc = (5, 70, 40)
+    n = [a * b for a, b in zip(nc, m)]
+    xf, yf, zf = inputs.uniform_faces(n[0]), inputs.uniform_faces(n[1]), inputs.tanh_faces(n[2], 1.5)
+    walls = side_y == "walls"
+    g = O.Grid(xf, yf, zf, m, periodic=(True, not walls, False))
+    rng = np.random.default_rng(33)
+    ny_faces = n[1] + (1 if walls else 0)   # the oracle keeps the high wall face of a walled axis
+    ys = [rng.standard_normal((n[2], n[1], n[0])), rng.standard_normal((n[2], ny_faces, n[0])),
+          rng.standard_normal((n[2] + 1, n[1], n[0]))]
+    if walls:
+        ys[1][:, 0, :] = 0.0
+        ys[1][:, -1, :] = 0.0
+    want = O.refine_velocity_transpose(g, *ys)
+    if walls:
+        ys[1] = ys[1][:, :-1, :]   # the library keeps the low wall face only
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with Context(xf, yf, zf, m, 1e6, 4.38, 1e-5, side_y=side_y) as ctx:
+        gU, gV, gW = [host(t) for t in ctx.interpolate_velocity_backward(*[dev(y) for y in ys])]
+    assert rel_max(gU, want[0]) <= FP64_TOL
+    assert rel_max(gW, want[2]) <= FP64_TOL
+    if walls:
+        # the low wall face is taken as zero by the forward map: zero gradient
+        assert np.all(gV[:, 0] == 0)
+        assert rel_max(gV[:, 1:], want[1][:, 1:-1]) <= FP64_TOL
+    else:
+        assert rel_max(gV, want[1]) <= FP64_TOL
