@@ -22,12 +22,13 @@
 // no column is held whole anywhere, so the column height is not limited by
 // registers.
 //
-// Workgroup: TY wavefronts, one per y row of a tile of 64 x columns by TY
-// rows; lane l of wavefront r owns column i0 + l of row j0 + r.  The rows
-// beside the tile (j0 - 1 and j0 + TY) are back-substituted by the first and
-// the last wavefront as a second column each, the columns beside each row
-// (i0 - 1 and i0 + 64) by lanes 0 and 63 as one more column (the other lanes
-// repeat their own column in the same instructions, which the cache serves).
+// Workgroup: TX x TY wavefronts over a tile of 64 TX x columns by TY rows;
+// lane l of the wavefront of segment c and row r owns column i0 + 64 c + l of
+// row j0 + r.  The rows beside the tile (j0 - 1 and j0 + TY) are
+// back-substituted by the wavefronts of the first and the last row as a
+// second column each, the columns beside each segment (64 c - 1 and 64 c +
+// 64) by its lanes 0 and 63 as one more column (the other lanes repeat their
+// own column in the same instructions, which the cache serves).
 // Lanes and rows past a ragged end take the periodic continuation and never
 // store.  The step needs x and y periodic with uniform widths and the plain
 // second-order method (no explicit z share, no fourth-order faces).
@@ -114,15 +115,18 @@ struct Rh {
   T u0, u1, v0, v1, wf;
 };
 
-template <typename T, int TY, bool DOWN, bool FIRST, int PF>
-__global__ void __launch_bounds__(64 * TY) sweep_kernel(SweepArgs<T> A) {
+template <typename T, int TX, int TY, bool DOWN, bool FIRST, int PF>
+__global__ void __launch_bounds__(64 * TX * TY) sweep_kernel(SweepArgs<T> A) {
   static_assert(TY >= 2, "the halo rows belong to two different wavefronts");
-  __shared__ T shn[2][TY + 2][64];   // theta^m rows of a level (double-buffered by level parity)
-  __shared__ T shp[2][TY + 2][64];   // theta^{m-1} rows
+  constexpr int W = 64 * TX;          // tile width (TX wavefronts per row)
+  __shared__ T shn[2][TY + 2][W];     // theta^m rows of a level (double-buffered by level parity)
+  __shared__ T shp[2][TY + 2][W];     // theta^{m-1} rows
   const int lane = threadIdx.x;
-  const int r = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int r = wv / TX, cx = wv - r * TX;   // tile row and 64-column segment of this wavefront
+  const int lx = cx * 64 + lane;             // column inside the tile
   const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int ntx = (nx + 63) / 64, nty = (ny + TY - 1) / TY;
+  const int ntx = (nx + W - 1) / W, nty = (ny + TY - 1) / TY;
   // tile walk: bands of A.band x tiles, walked row tile by row tile, x fastest
   // in a band; consecutive tiles of the walk go to one XCD
   const int t = xcd_remap(blockIdx.x, ntx * nty);
@@ -132,7 +136,7 @@ __global__ void __launch_bounds__(64 * TY) sweep_kernel(SweepArgs<T> A) {
   const int wb = min(A.band, ntx - bnd * A.band);
   const int jt = rt / wb;
   const int xt = bnd * A.band + (rt - jt * wb);
-  const int i_raw = xt * 64 + lane, j_raw = jt * TY + r;
+  const int i_raw = xt * W + lx, j_raw = jt * TY + r;
   const bool act = i_raw < nx && j_raw < ny;
   const int i = i_raw % nx, j = j_raw % ny;
   const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
@@ -216,15 +220,15 @@ __global__ void __launch_bounds__(64 * TY) sweep_kernel(SweepArgs<T> A) {
     }
     // 2. rows to LDS (double-buffered by level parity: one barrier per level)
     const int b = s & 1;
-    shn[b][r + 1][lane] = tc;
-    shp[b][r + 1][lane] = cur.pc;
+    shn[b][r + 1][lx] = tc;
+    shp[b][r + 1][lx] = cur.pc;
     if (hlo) {
-      shn[b][0][lane] = th;
-      shp[b][0][lane] = cur.ph;
+      shn[b][0][lx] = th;
+      shp[b][0][lx] = cur.ph;
     }
     if (hhi) {
-      shn[b][TY + 1][lane] = th;
-      shp[b][TY + 1][lane] = cur.ph;
+      shn[b][TY + 1][lx] = th;
+      shp[b][TY + 1][lx] = cur.ph;
     }
     // 3. the level behind: its z stencil closes with this level's theta^m
     if (s > 0) {
@@ -235,10 +239,10 @@ __global__ void __launch_bounds__(64 * TY) sweep_kernel(SweepArgs<T> A) {
     __syncthreads();
     // 4. this level's stencil values: rows from LDS, columns by lane shifts
     q1.tc = tc;
-    q1.tym = shn[b][r][lane];
-    q1.typ = shn[b][r + 2][lane];
-    q1.pym = shp[b][r][lane];
-    q1.pyp = shp[b][r + 2][lane];
+    q1.tym = shn[b][r][lx];
+    q1.typ = shn[b][r + 2][lx];
+    q1.pym = shp[b][r][lx];
+    q1.pyp = shp[b][r + 2][lx];
     const T tl = shr(tc), trr = shl(tc), pl = shr(cur.pc), pr = shl(cur.pc), ur = shl(cur.u0);
     q1.txm = lane == 0 ? tx : tl;
     q1.txp = lane == 63 ? tx : trr;
@@ -293,14 +297,22 @@ __global__ void __launch_bounds__(256) backsub_kernel(const T* __restrict__ e, T
 namespace {
 using namespace sweep;
 
-// Tiles of 16 rows (one 1024-thread workgroup per CU), walked in bands of 8 x
-// tiles, with loads one level ahead in FP64 and three in FP32.  Timed at
-// 1024 x 1024 x 512 against tiles of 4, 8 and 12 rows, bands of 1, 2 and 4 and
-// prefetch depths of 1 to 4: on one machine 16-row tiles took 5.75 ms (FP64)
-// and 3.01 ms (FP32) per step against 6.35 and 3.22 ms with 8 rows; two levels
-// ahead in FP64 (128 VGPRs) was 14% slower; bands of 8 were 2-5% faster than 4.
-constexpr int kSweepRows = kSweepTileRows;  // wavefronts (y rows) per workgroup
-constexpr int kSweepBand = 8;   // x tiles per band of the tile walk
+// Tiles of 1024 columns (one 1024-thread workgroup per CU): 256 x 4 walked in
+// bands of 4 x tiles in FP64, 128 x 8 in bands of 8 in FP32, with loads one
+// level ahead in FP64 and three in FP32.  Timed at 1024 x 1024 x 512 in one
+// run against 64 x 16 (bands of 8 and 16), 128 x 8 and 256 x 4: in FP64 the
+// shapes were within 2% (5.78 ms per step for 256 x 4), in FP32 the 128- and
+// 256-wide tiles took 2.66-2.75 ms against 2.93-3.14 ms for 64 x 16 (longer
+// contiguous rows per level).  Earlier: 64 x 16 against 64 x 4, 8 and 12, two
+// levels ahead in FP64 (128 VGPRs) 14% slower.
+template <typename T>
+struct SweepTile {
+  static constexpr bool f64 = sizeof(T) == 8;
+  static constexpr int segs = sweep_tile_segs(f64);   // 64-column wavefronts per tile row
+  static constexpr int rows = sweep_tile_rows(f64);   // tile rows
+  static constexpr int band = f64 ? 4 : 8;            // x tiles per band of the tile walk
+  static constexpr int pf = f64 ? 1 : 3;              // levels of loads ahead
+};
 
 template <typename T>
 const Geom<T>& geom(const mr_ctx* c);
@@ -347,17 +359,16 @@ hipError_t sweep_t(mr_ctx* c, int64_t m, bool first, bool down, const void* src,
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
-  constexpr int TY = kSweepRows;
-  const int ntx = (c->nx + 63) / 64, nty = (c->ny + TY - 1) / TY;
-  a.band = kSweepBand < ntx ? kSweepBand : ntx;
-  const dim3 grid((unsigned)(ntx * nty)), block(64, TY);
-  constexpr int PF = sizeof(T) == 8 ? 1 : 3;   // levels of loads ahead
+  constexpr int TX = SweepTile<T>::segs, TY = SweepTile<T>::rows, PF = SweepTile<T>::pf;
+  const int ntx = (c->nx + 64 * TX - 1) / (64 * TX), nty = (c->ny + TY - 1) / TY;
+  a.band = SweepTile<T>::band < ntx ? SweepTile<T>::band : ntx;
+  const dim3 grid((unsigned)(ntx * nty)), block(64, TX * TY);
   if (first) {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TY, true, true, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TY, false, true, PF>), grid, block, 0, s, a);
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, true, PF>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, true, PF>), grid, block, 0, s, a);
   } else {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TY, true, false, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TY, false, false, PF>), grid, block, 0, s, a);
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, false, PF>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, false, PF>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }

@@ -700,7 +700,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     c->sw[k] = sweep_ptrs(base, swo[k]);
   }
   // step sequences run as column sweeps where the line solver cannot take the
-  // columns, and where the sweep's tiles (one workgroup of 64 x 16 columns per
+  // columns, and where the sweep's tiles (one workgroup of 1024 columns per
   // CU at a time) fill the GPU at least three times over: with fewer, the
   // last round of tiles leaves CUs idle (measured at 576 x 576 columns, 324
   // tiles on 256 CUs: 12% slower than the line solver; 1024 x 1024, 1024
@@ -708,7 +708,9 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
     cus = 256;
-  const int64_t tiles = (int64_t)((c->nx + 63) / 64) * ((c->ny + mr::kSweepTileRows - 1) / mr::kSweepTileRows);
+  const bool f64 = c->precision == MR_FP64;
+  const int tw = 64 * mr::sweep_tile_segs(f64), th = mr::sweep_tile_rows(f64);
+  const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + th - 1) / th);
   c->sweep_pref = desc->step_method == 2 ||
                   (desc->step_method == 0 && P.sweep_ok && (nch == 0 || tiles >= 3 * (int64_t)cus));
   c->sweep_single = nch == 0 || desc->step_method == 2;

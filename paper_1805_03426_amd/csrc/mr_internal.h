@@ -18,8 +18,11 @@ enum StepKind { KIND_STARTUP = 0, KIND_LEAPFROG = 1, KIND_AVERAGE = 2, NKINDS = 
 constexpr int kMaxChunks = 16;
 constexpr int kChunkLens[] = {32, 36, 40};
 constexpr int kWave = 64;
-// rows of a column-sweep tile (64 x columns by this many y rows)
-constexpr int kSweepTileRows = 16;
+// a column-sweep tile: sweep_tile_segs segments of 64 x columns by
+// sweep_tile_rows y rows, one wavefront per segment and row (1024 columns per
+// tile in either precision: 256 x 4 in FP64, 128 x 8 in FP32)
+constexpr int sweep_tile_segs(bool fp64) { return fp64 ? 4 : 2; }
+constexpr int sweep_tile_rows(bool fp64) { return fp64 ? 4 : 8; }
 
 // Grid tables of one precision (device pointers into the context's table block).
 template <typename T>
