@@ -60,10 +60,10 @@ def workload_inputs(w):
 
 
 def kernel_source_hash(method="sweep"):
-    """Hash of the sources that define the step kernel of a method (its code,
-    the shared header and the host tables), to tell whether the committed
-    counters of that kernel are stale."""
-    names = {"sweep": ("k_sweep.hip", "mr_internal.h", "mr_api.hip"),
+    """Hash of the sources that define the step kernel of a method and its
+    launch shape (the kernel code, its launch code and the shared header), to
+    tell whether the committed counters of that kernel are stale."""
+    names = {"sweep": ("k_sweep.hip", "mr_internal.h"),
              "line": ("line_kernel.h", "k_line_fwd.hip", "k_step.hip", "mr_internal.h", "mr_api.hip")}[method]
     h = hashlib.sha256()
     for name in names:
