@@ -65,6 +65,24 @@ def test_dissipation_parity(prec, bc):
         assert abs(got[k] - want[k]) <= tol * abs(want["nu_t"]), (k, got[k], want[k])
 
 
+@pytest.mark.parametrize("prec,nc", [("fp64", (640, 80, 120)), ("fp32", (70, 17, 40)), ("fp64", (1, 1, 9))])
+def test_dissipation_parity_tiles(prec, nc):
+    """Nu_T over several tiles of 64 columns by 8 rows, ragged in x and y, and
+    over level ranges of 11 (load batches of 4, 4 and 3 levels) and of 1, and
+    on a single column (its own x and y neighbour)."""
+    print("case dissipation tiles", prec, nc, flush=True)
+    case = Case(nc, (1, 1, 1), 1.5, kmax=1, precision=prec, random_velocity=True, dt=1e-5)
+    rng = np.random.default_rng(7)
+    th = case.th0 + 0.1 * rng.standard_normal(case.th0.shape)
+    if prec == "fp32":
+        th = th.astype(np.float32).astype(np.float64)
+    want = thermal_dissipation(case.g, case.p, th)
+    with case.ctx() as ctx:
+        _, got = ctx.thermal_dissipation(case.d(th))
+    for k in ("nu_t", "gx2", "gy2", "gz2"):
+        assert abs(got[k] - want[k]) <= 1e-12 * abs(want["nu_t"]), (k, got[k], want[k])
+
+
 def test_dissipation_of_conduction_is_one():
     case = Case((8, 6, 9), (2, 2, 2), 2.5, kmax=1, random_velocity=True)
     th = np.broadcast_to(1.0 - case.g.z.c[:, None, None], case.g.shape).copy()
@@ -125,8 +143,9 @@ def test_coarse_step_parity(prec):
         prev, cur = ctx.coarse_step(mt, mt, *lv[1], *lv[2], uvw, ring, prev, cur, tc)
         assert rel_l2(host(ring[cur]), c2) <= tol and rel_l2(host(ring[prev]), p2) <= tol
         assert rel_max(host(tc), tc2) <= tol
-        # the last refined velocity is the refinement of the new level
-        want = O.refine_velocity(case.g, U2, V2, W2)
+        # the last refined velocity is the one of the last sub-step: fraction
+        # (M_t - 1) / M_t between the two levels
+        want = O.refine_velocity(case.g, *blend_velocity(U1, V1, W1, U2, V2, W2, mt - 1, mt))
         for a, b in zip(uvw, want):
             assert rel_max(host(a), b) <= tol
 
