@@ -169,24 +169,45 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
   if (k > 0) A.gw[row + i] += sw;
 }
 
-// Second-order faces: a wavefront owns 64 columns of one row and a segment of
-// ZS z levels.  For each step in turn it loads theta and mu on the segment's
-// levels (and the level below it) and adds every step's contribution to
-// per-level accumulators in registers; the loads of a step are independent of
-// each other, so they are all in flight together.  The column to the left
-// comes from the lane beside it (lane 0 loads it in the instruction where the
-// others re-read their own value) and the row below from the wavefront beside
-// it in the workgroup (cache).  gu, gv, gw are then updated once per level.
-constexpr int kGradRows = 4;   // wavefronts (rows of 64 columns) per workgroup
+// Second-order faces: a workgroup of kGradRows wavefronts owns a tile of 64
+// columns by kGradRows rows and walks a run of consecutive z segments of ZS
+// levels.  For each segment and step in turn every wavefront loads theta and
+// mu of its row on the segment's levels, the first wavefront also the row
+// below the tile, and publishes them in LDS, where the wavefront of the next
+// row finds its y neighbours: a row is read from memory once per step and
+// segment (the y halo is one row in kGradRows).  The level below a segment is
+// loaded for the first segment of the run and then carried in registers from
+// the segment before (CARRY; without it, loaded for every segment).  The loads
+// of a step are independent of each other, so they are all in flight
+// together.  The column to the left comes from the lane beside it (lane 0
+// loads it).  The LDS buffer alternates from step to step, one barrier per
+// step.  Every step's contribution goes to per-level accumulators in
+// registers; gu, gv, gw are updated once per level.
+constexpr int kGradRows = 16;   // wavefronts (rows of 64 columns) per workgroup
+constexpr int kGradRun = 8;     // FP32: segments per workgroup
+constexpr int kGradWaves = 4;   // wavefronts per SIMD to fit (128 VGPRs)
 
-template <typename T, int KM, int ZS>
-__global__ void __launch_bounds__(64 * kGradRows) grad_seg(GradArgs<T> A) {
+template <typename T, int KM, int ZS, bool CARRY>
+__global__ void __launch_bounds__(64 * kGradRows, kGradWaves) grad_seg(GradArgs<T> A, int run) {
+  __shared__ T lt[2][ZS][kGradRows + 1][kWave];   // theta rows by step parity, level, tile row + 1
+  __shared__ T lm[2][ZS][kGradRows + 1][kWave];   // mu rows
+  // the steps' field pointers and weights, read from LDS at every use so that
+  // they do not stay live in scalar registers across the segment loop
+  __shared__ const T* sptr[2][KM];
+  __shared__ T stau[KM];
+  if (threadIdx.x < KM && (int)threadIdx.x < A.count) {
+    sptr[0][threadIdx.x] = A.th[threadIdx.x];
+    sptr[1][threadIdx.x] = A.mu[threadIdx.x];
+    stau[threadIdx.x] = A.tau[threadIdx.x];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int r = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int ntx = (nx + kWave - 1) / kWave, nty = (ny + kGradRows - 1) / kGradRows;
-  const int tile = blockIdx.x % (ntx * nty);
-  const int k0 = blockIdx.x / (ntx * nty) * ZS;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = b % (ntx * nty);
+  const int seg0 = b / (ntx * nty) * run;   // first segment of this workgroup's run
   const int xt = tile % ntx, jt = tile / ntx;
   const int i_raw = xt * kWave + lane, j_raw = jt * kGradRows + r;
   const bool act = i_raw < nx && j_raw < ny;
@@ -195,76 +216,119 @@ __global__ void __launch_bounds__(64 * kGradRows) grad_seg(GradArgs<T> A) {
   const int i = i_raw % nx, j = j_raw % ny;
   const int im = i == 0 ? (wx ? 0 : nx - 1) : i - 1;
   const int jm = j == 0 ? (wy ? 0 : ny - 1) : j - 1;
+  // the row below the tile (the first wavefront loads it; on a walled y axis
+  // the tile at j = 0 takes its own first row: that face gets no gradient)
+  const int j0 = jt * kGradRows;
+  const int jh = j0 == 0 ? (wy ? 0 : ny - 1) : j0 - 1;
   const int nxy = nx * ny;
   constexpr unsigned sz = sizeof(T);
   const unsigned oc = (unsigned)(j * nx + i) * sz;
-  const unsigned oxe = lane == 0 ? (unsigned)(j * nx + im) * sz : oc;   // lane 0: its left column
-  const unsigned oym = (unsigned)(jm * nx + i) * sz;
+  const unsigned oxe = (unsigned)(j * nx + im) * sz;   // lane 0: its left column
+  const unsigned oh = (unsigned)(jh * nx + i) * sz;
   const T half = T(0.5);
   const T ihx = A.g.ihx[i], ihxm = A.g.ihx[im], ihy = A.g.ihy[j], ihym = A.g.ihy[jm];
+  const bool zu = wx && i == 0, zv = wy && j == 0;   // side-wall faces: no gradient
   auto at = [&](const T* f, int k, unsigned off) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(f + (size_t)k * nxy) + off);
   };
-  T ihz[ZS + 1];   // 1/hz of the level below the segment and of its levels
+  T cbt[CARRY ? KM : 1], cbm[CARRY ? KM : 1];   // each step's theta and mu on the level below the segment
+  int p = 0;                                    // LDS buffer of the next step
+  for (int sg = 0; sg < run; ++sg) {
+    const int k0 = (seg0 + sg) * ZS;
+    if (k0 >= nz) break;
+    const bool below = !CARRY || sg == 0;       // load the level below (else carried)
+    T ihz[ZS + 1];   // 1/hz of the level below the segment and of its levels (scalar loads)
 #pragma unroll
-  for (int z = 0; z <= ZS; ++z) {
-    const int k = min(max(k0 + z - 1, 0), nz - 1);
-    ihz[z] = A.g.ihz[k];
-  }
-  T su[ZS], sv[ZS], sw[ZS];
+    for (int z = 0; z <= ZS; ++z) {
+      const int k = min(max(k0 + z - 1, 0), nz - 1);
+      ihz[z] = ((const __attribute__((address_space(4))) T*)(A.g.ihz))[k];
+    }
+    T su[ZS], sv[ZS], sw[ZS];
 #pragma unroll
-  for (int z = 0; z < ZS; ++z) su[z] = sv[z] = sw[z] = T(0);
+    for (int z = 0; z < ZS; ++z) su[z] = sv[z] = sw[z] = T(0);
 #pragma unroll
-  for (int s = 0; s < KM; ++s) {
-    if (s < A.count) {
-      const T* th = A.th[s];
-      const T* mu = A.mu[s];
-      const T tau = A.tau[s];
-      // levels k0-1 .. k0+ZS-1 (clamped into the grid; the ones outside add nothing)
-      T tc[ZS + 1], mc[ZS + 1], te[ZS], me[ZS], ty[ZS], my[ZS];
-#pragma unroll
-      for (int z = 0; z <= ZS; ++z) {
-        const int k = min(max(k0 + z - 1, 0), nz - 1);
-        tc[z] = at(th, k, oc);
-        mc[z] = at(mu, k, oc);
-        if (z > 0) {
-          te[z - 1] = at(th, k, oxe);
-          me[z - 1] = at(mu, k, oxe);
-          ty[z - 1] = at(th, k, oym);
-          my[z - 1] = at(mu, k, oym);
+    for (int s = 0; s < KM; ++s) {
+      if (s < A.count) {
+        const T* th = sptr[0][s];
+        const T* mu = sptr[1][s];
+        const T tau = stau[s];
+        // levels k0-1 .. k0+ZS-1 (clamped into the grid; the ones outside add nothing)
+        T tc[ZS + 1], mc[ZS + 1], te[ZS], me[ZS], th_h[ZS], mu_h[ZS];
+        if (below) {
+          const int k = max(k0 - 1, 0);
+          tc[0] = at(th, k, oc);
+          mc[0] = at(mu, k, oc);
+        } else if constexpr (CARRY) {
+          tc[0] = cbt[s];
+          mc[0] = cbm[s];
         }
-      }
 #pragma unroll
-      for (int z = 0; z < ZS; ++z) {
-        const T t = tc[z + 1], m = mc[z + 1];
-        const T tl = line::lane_shr(t), ml = line::lane_shr(m);
-        const T txm = lane == 0 ? te[z] : tl, mxm = lane == 0 ? me[z] : ml;
-        su[z] += tau * (half * (txm + t)) * (m * ihx - mxm * ihxm);
-        sv[z] += tau * (half * (ty[z] + t)) * (m * ihy - my[z] * ihym);
-        sw[z] += tau * (half * (tc[z] + t)) * (m * ihz[z + 1] - mc[z] * ihz[z]);
+        for (int z = 1; z <= ZS; ++z) {
+          const int k = min(k0 + z - 1, nz - 1);
+          tc[z] = at(th, k, oc);
+          mc[z] = at(mu, k, oc);
+          if (lane == 0) {
+            te[z - 1] = at(th, k, oxe);
+            me[z - 1] = at(mu, k, oxe);
+          }
+          if (r == 0) {
+            th_h[z - 1] = at(th, k, oh);
+            mu_h[z - 1] = at(mu, k, oh);
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+          lt[p][z][r + 1][lane] = tc[z + 1];
+          lm[p][z][r + 1][lane] = mc[z + 1];
+          if (r == 0) {
+            lt[p][z][0][lane] = th_h[z];
+            lm[p][z][0][lane] = mu_h[z];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+          const T t = tc[z + 1], m = mc[z + 1];
+          const T tl = line::lane_shr(t), ml = line::lane_shr(m);
+          const T txm = lane == 0 ? te[z] : tl, mxm = lane == 0 ? me[z] : ml;
+          const T ty = lt[p][z][r][lane], my = lm[p][z][r][lane];
+          su[z] += tau * (half * (txm + t)) * (m * ihx - mxm * ihxm);
+          sv[z] += tau * (half * (ty + t)) * (m * ihy - my * ihym);
+          sw[z] += tau * (half * (tc[z] + t)) * (m * ihz[z + 1] - mc[z] * ihz[z]);
+        }
+        if constexpr (CARRY) {
+          cbt[s] = tc[ZS];
+          cbm[s] = mc[ZS];
+        }
+        p ^= 1;
       }
     }
-  }
-  const bool zu = wx && i == 0, zv = wy && j == 0;   // side-wall faces: no gradient
 #pragma unroll
-  for (int z = 0; z < ZS; ++z) {
-    const int k = k0 + z;
-    if (act && k < nz) {
-      const size_t o = (size_t)k * nxy + (size_t)j * nx + i;
-      A.gu[o] += zu ? T(0) : su[z];
-      A.gv[o] += zv ? T(0) : sv[z];
-      if (k > 0) A.gw[o] += sw[z];   // the bottom wall face carries no flux
+    for (int z = 0; z < ZS; ++z) {
+      const int k = k0 + z;
+      if (act && k < nz) {
+        const size_t o = (size_t)k * nxy + (size_t)j * nx + i;
+        A.gu[o] += zu ? T(0) : su[z];
+        A.gv[o] += zv ? T(0) : sv[z];
+        if (k > 0) A.gw[o] += sw[z];   // the bottom wall face carries no flux
+      }
     }
   }
 }
 
+// Segments of 8 levels in FP32 (runs of up to 8 segments, the level below
+// carried), of 4 in FP64 (no carry: its registers would not fit beside the
+// accumulators at 1024 threads per workgroup).
 template <typename T, int KM>
 void launch_grad_seg(mr_ctx* c, const GradArgs<T>& a, hipStream_t s) {
-  constexpr int ZS = sizeof(T) == 8 ? 4 : 8;   // levels per segment
+  constexpr bool f64 = sizeof(T) == 8;
+  constexpr int ZS = f64 ? 4 : 8;   // levels per segment
   const int ntx = (c->nx + kWave - 1) / kWave, nty = (c->ny + kGradRows - 1) / kGradRows;
   const int nseg = (c->nz + ZS - 1) / ZS;
-  const dim3 grid((unsigned)((int64_t)ntx * nty * nseg)), block(kWave * kGradRows);
-  hipLaunchKernelGGL((grad_seg<T, KM, ZS>), grid, block, 0, s, a);
+  const int run = f64 ? 1 : std::min(nseg, kGradRun);
+  const int nrun = (nseg + run - 1) / run;
+  const dim3 grid((unsigned)((int64_t)ntx * nty * nrun)), block(kWave * kGradRows);   // 139 KB of LDS
+  hipLaunchKernelGGL((grad_seg<T, KM, ZS, !f64>), grid, block, 0, s, a, run);
 }
 
 template <typename T>
