@@ -2,11 +2,12 @@
 
 ``ScalarRollout`` is a torch.autograd.Function whose forward refines the
 coarse velocity once (it is frozen over the rollout), runs N scalar steps on a
-ring of three buffers and keeps the pair (theta^{n-1}, theta^n) every K steps
-and every state of the last segment; each kept state is written straight into
-a buffer of its own, so nothing is copied.  Its backward walks the checkpoint
-segments in reverse: it recomputes the states of each segment but the last
-from its checkpoint, runs the fused reverse step of each
+ring of three buffers as one step sequence, and keeps the pair
+(theta^{n-1}, theta^n) every K steps and every state of the last segment; each
+kept state is written straight into a buffer of its own, so nothing is
+copied.  Its backward walks the checkpoint segments in reverse: it recomputes
+the states of each segment but the last from its checkpoint (one step
+sequence each), runs the fused reverse step of each
 step (transposed implicit solve fused with the transposed stencils), adds the
 segment's dense face-velocity gradient from the stored (theta^n, mu^n)
 pairs (one library call per group of at most 16 steps), and finally maps the dense face gradient to the coarse faces with the
@@ -36,18 +37,23 @@ class ScalarRollout(torch.autograd.Function):
         prev = cur = th0
         ckpts = {0: (None, th0)}
         tail = {0: th0} if last == 0 else {}
+        outs = []
         for n in range(nsteps):
             m = n + 1
             if m % K == 0 or (m + 1) % K == 0 or last <= m < nsteps:
                 out = mr.empty(mr.shape_cell)
             else:
                 out = next(b for b in pool if b is not prev and b is not cur)
-            mr.scalar_step(n, prev, cur, out, u, v, w)
+            outs.append(out)
             prev, cur = cur, out
             if m < nsteps and m % K == 0:
                 ckpts[m] = (prev, cur)
             if last <= m < nsteps:
                 tail[m] = cur
+        # the whole rollout is one step sequence (column sweeps where the
+        # library prefers them); every output differs from the two levels
+        # before it
+        mr.scalar_steps(0, None, th0, outs, u, v, w)
         fctx.mr = mr
         fctx.nsteps = nsteps
         fctx.K = K
@@ -78,13 +84,11 @@ class ScalarRollout(torch.autograd.Function):
                 # recompute theta^s .. theta^{e-1} from the checkpoint
                 pprev, pcur = fctx.ckpts[s]
                 states = {s: pcur}
-                prev = pprev if pprev is not None else pcur
-                cur = pcur
-                for n in range(s, e - 1):
-                    out = mr.empty(mr.shape_cell)
-                    mr.scalar_step(n, prev, cur, out, u, v, w)
+                outs = [mr.empty(mr.shape_cell) for _ in range(s, e - 1)]
+                if outs:
+                    mr.scalar_steps(s, pprev, pcur, outs, u, v, w)
+                for n, out in zip(range(s, e - 1), outs):
                     states[n + 1] = out
-                    prev, cur = cur, out
             # reverse steps e-1 .. s; mu^n is kept for the velocity gradient
             mus = {}
             for n in range(e - 1, s - 1, -1):

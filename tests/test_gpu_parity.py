@@ -91,9 +91,9 @@ class Case:
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
 
-    def ctx(self):
+    def ctx(self, step_method="auto"):
         return _ctx_cls()(self.xf, self.yf, self.zf, self.m, self.ra, self.pr, self.dt, n_avg=self.n_avg,
-                          bc_bot=self.bc[0], bc_top=self.bc[1], precision=self.precision)
+                          bc_bot=self.bc[0], bc_top=self.bc[1], precision=self.precision, step_method=step_method)
 
     def d(self, x):
         return dev(x, self.dtype)
@@ -366,18 +366,23 @@ def test_adjoint_parity_fp32(stretch_x):
         assert rel_l2(a, b) <= FP32_TOL
 
 
-@pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (7, 1), (7, 16), (6, 3), (1, 3), (5, 5), (20, 18)])
-def test_rollout_checkpoint_segments(nsteps, ckpt):
+@pytest.mark.parametrize("nsteps,ckpt,method", [(7, 3, "auto"), (7, 1, "auto"), (7, 16, "auto"), (6, 3, "auto"),
+                                                (1, 3, "auto"), (5, 5, "auto"), (20, 18, "auto"), (7, 3, "sweep"),
+                                                (20, 6, "sweep"), (2, 1, "sweep")])
+def test_rollout_checkpoint_segments(nsteps, ckpt, method):
     """The autograd rollout (checkpoint pairs and the last segment kept by the
-    forward pass, the other segments recomputed) against the oracle's discrete
-    adjoint, for segment counts of one to seven, a ragged last segment, a
-    single step and segments longer than one velocity-gradient call (FP64)."""
-    print("case rollout", nsteps, ckpt, flush=True)
+    forward pass, the other segments recomputed; the forward pass and each
+    recomputation one step sequence) against the oracle's discrete adjoint,
+    for segment counts of one to seven, a ragged last segment, a single step
+    and segments longer than one velocity-gradient call (FP64), with the
+    sequences on the line solver and on the column sweeps."""
+    print("case rollout", nsteps, ckpt, method, flush=True)
     from paper_1805_03426_amd.autograd import rollout
     case = Case((8, 6, 7), (2, 3, 2), 1.5, ra=1e4, kmax=2, n_avg=3)
     target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
     _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, nsteps, target)
-    with case.ctx() as ctx:
+    with case.ctx(method) as ctx:
+        assert ctx.step_method == ("sweep" if method == "sweep" else "line")
         th = case.d(case.th0).requires_grad_(True)
         U, V, W = (case.d(a).requires_grad_(True) for a in (case.U, case.V, case.W))
         out = rollout(ctx, th, U, V, W, nsteps, ckpt)
