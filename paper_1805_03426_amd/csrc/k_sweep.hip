@@ -297,21 +297,26 @@ __global__ void __launch_bounds__(256) backsub_kernel(const T* __restrict__ e, T
 namespace {
 using namespace sweep;
 
-// Tiles of 1024 columns (one 1024-thread workgroup per CU): 256 x 4 walked in
-// bands of 4 x tiles in FP64, 128 x 8 in bands of 8 in FP32, with loads one
-// level ahead in FP64 and three in FP32.  Timed at 1024 x 1024 x 512 in one
-// run against 64 x 16 (bands of 8 and 16), 128 x 8 and 256 x 4: in FP64 the
-// shapes were within 2% (5.78 ms per step for 256 x 4), in FP32 the 128- and
-// 256-wide tiles took 2.66-2.75 ms against 2.93-3.14 ms for 64 x 16 (longer
-// contiguous rows per level).  Earlier: 64 x 16 against 64 x 4, 8 and 12, two
-// levels ahead in FP64 (128 VGPRs) 14% slower.
+// Tile shapes, in the order each precision prefers them: FP64 256 x 4, 192 x 4,
+// 128 x 8, 64 x 16; FP32 128 x 8, 192 x 4, 64 x 16.  The first whose
+// width divides N_x is taken (else the one that leaves the fewest idle
+// lanes): lanes past a ragged end still load, so a ragged tile costs reads.
+// Timed in one run at 1024 x 1024 x 512: in FP64 the shapes were within 2%
+// (5.78 ms per step for 256 x 4), in FP32 the 128- and 256-wide tiles took
+// 2.66-2.75 ms against 2.93-3.14 ms for 64 x 16 (longer contiguous rows per
+// level).  At 576^3 (M = 3), 192 x 4 took 2.36 ms (FP64) and 1.00 ms (FP32)
+// against 2.84 and 1.26 ms for the ragged 256 x 4 and 128 x 8 and 2.51 and
+// 1.17 ms for 64 x 8.  Tiles are walked in bands of 4 x tiles in FP64, 8 in
+// FP32; loads run one level ahead in FP64 and three in FP32 (two ahead in
+// FP64, 128 VGPRs, was 14% slower).
+constexpr int kOrder64[] = {0, 1, 2, 3};
+constexpr int kOrder32[] = {2, 1, 3};   // 256 x 4 in FP32 was no faster than 128 x 8
+
 template <typename T>
 struct SweepTile {
   static constexpr bool f64 = sizeof(T) == 8;
-  static constexpr int segs = sweep_tile_segs(f64);   // 64-column wavefronts per tile row
-  static constexpr int rows = sweep_tile_rows(f64);   // tile rows
-  static constexpr int band = f64 ? 4 : 8;            // x tiles per band of the tile walk
-  static constexpr int pf = f64 ? 1 : 3;              // levels of loads ahead
+  static constexpr int band = f64 ? 4 : 8;   // x tiles per band of the tile walk
+  static constexpr int pf = f64 ? 1 : 3;     // levels of loads ahead
 };
 
 template <typename T>
@@ -320,6 +325,22 @@ template <>
 const Geom<double>& geom<double>(const mr_ctx* c) { return c->g64; }
 template <>
 const Geom<float>& geom<float>(const mr_ctx* c) { return c->g32; }
+
+template <typename T, int TX, int TY>
+hipError_t launch_shape(int nx, int ny, bool first, bool down, SweepArgs<T>& a, hipStream_t s) {
+  constexpr int PF = SweepTile<T>::pf;
+  const int ntx = (nx + 64 * TX - 1) / (64 * TX), nty = (ny + TY - 1) / TY;
+  a.band = SweepTile<T>::band < ntx ? SweepTile<T>::band : ntx;
+  const dim3 grid((unsigned)(ntx * nty)), block(64, TX * TY);
+  if (first) {
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, true, PF>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, true, PF>), grid, block, 0, s, a);
+  } else {
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, false, PF>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, false, PF>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t sweep_t(mr_ctx* c, int64_t m, bool first, bool down, const void* src, const void* lag,
@@ -359,18 +380,14 @@ hipError_t sweep_t(mr_ctx* c, int64_t m, bool first, bool down, const void* src,
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
-  constexpr int TX = SweepTile<T>::segs, TY = SweepTile<T>::rows, PF = SweepTile<T>::pf;
-  const int ntx = (c->nx + 64 * TX - 1) / (64 * TX), nty = (c->ny + TY - 1) / TY;
-  a.band = SweepTile<T>::band < ntx ? SweepTile<T>::band : ntx;
-  const dim3 grid((unsigned)(ntx * nty)), block(64, TX * TY);
-  if (first) {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, true, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, true, PF>), grid, block, 0, s, a);
-  } else {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, false, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, false, PF>), grid, block, 0, s, a);
+  switch (c->sweep_shape) {
+    case 0:
+      if constexpr (sizeof(T) == 8) return launch_shape<T, kSweepShape[0].segs, kSweepShape[0].rows>(c->nx, c->ny, first, down, a, s);
+      return hipErrorInvalidValue;   // not an FP32 shape
+    case 1: return launch_shape<T, kSweepShape[1].segs, kSweepShape[1].rows>(c->nx, c->ny, first, down, a, s);
+    case 2: return launch_shape<T, kSweepShape[2].segs, kSweepShape[2].rows>(c->nx, c->ny, first, down, a, s);
+    default: return launch_shape<T, kSweepShape[3].segs, kSweepShape[3].rows>(c->nx, c->ny, first, down, a, s);
   }
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -386,6 +403,23 @@ hipError_t backsub_t(mr_ctx* c, int64_t m, bool down, const void* e, void* out, 
 }
 
 }  // namespace
+
+int sweep_pick_shape(int nx, bool fp64) {
+  const int* order = fp64 ? kOrder64 : kOrder32;
+  const int n = fp64 ? (int)(sizeof(kOrder64) / sizeof(int)) : (int)(sizeof(kOrder32) / sizeof(int));
+  int best = order[0];
+  int64_t best_idle = -1;
+  for (int q = 0; q < n; ++q) {
+    const int w = 64 * kSweepShape[order[q]].segs;
+    const int64_t idle = (int64_t)(nx + w - 1) / w * w - nx;
+    if (idle == 0) return order[q];
+    if (best_idle < 0 || idle < best_idle) {
+      best = order[q];
+      best_idle = idle;
+    }
+  }
+  return best;
+}
 
 bool sweep_supported(const mr_ctx* c) {
   return c->uniform_xy && !c->wx && !c->wy && c->z_explicit == 0.0 && c->face_order == 2;

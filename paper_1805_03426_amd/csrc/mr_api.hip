@@ -700,19 +700,24 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     c->sw[k] = sweep_ptrs(base, swo[k]);
   }
   // step sequences run as column sweeps where the line solver cannot take the
-  // columns, and where the sweep's tiles (one workgroup of 1024 columns per
-  // CU at a time) fill the GPU at least three times over: with fewer, the
-  // last round of tiles leaves CUs idle (measured at 576 x 576 columns, 324
-  // tiles on 256 CUs: 12% slower than the line solver; 1024 x 1024, 1024
-  // tiles: 23% faster)
+  // columns, and where the sweep's tiles keep the GPU full: at least 16
+  // wavefronts per CU in all, and either one round of tiles (one workgroup
+  // per CU: the sweep kernels run 4 wavefronts per SIMD) or rounds at least
+  // 3/4 full.  Measured in one run: at 256^3 (64 tiles of 256 x 4 columns)
+  // the line solver is 2.7x (FP64) and 2.5x (FP32) faster; at 576^3 (432
+  // tiles of 192 x 4) the sweeps are 10% and 20% faster; at 1024 x 1024 x 512
+  // (1024 tiles) 27% and 25% faster.
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
     cus = 256;
   const bool f64 = c->precision == MR_FP64;
-  const int tw = 64 * mr::sweep_tile_segs(f64), th = mr::sweep_tile_rows(f64);
-  const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + th - 1) / th);
-  c->sweep_pref = desc->step_method == 2 ||
-                  (desc->step_method == 0 && P.sweep_ok && (nch == 0 || tiles >= 3 * (int64_t)cus));
+  c->sweep_shape = mr::sweep_pick_shape(c->nx, f64);
+  const mr::SweepShape sh = mr::kSweepShape[c->sweep_shape];
+  const int tw = 64 * sh.segs;
+  const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + sh.rows - 1) / sh.rows);
+  const int64_t slots = cus, rounds = (tiles + slots - 1) / slots;
+  const bool fills = tiles * sh.segs * sh.rows >= 16 * (int64_t)cus && (rounds == 1 || 4 * tiles >= 3 * rounds * slots);
+  c->sweep_pref = desc->step_method == 2 || (desc->step_method == 0 && P.sweep_ok && (nch == 0 || fills));
   c->sweep_single = nch == 0 || desc->step_method == 2;
   c->hx64 = (const double*)(base + o_hx64);
   c->areaw = (const double*)(base + o_hy64);

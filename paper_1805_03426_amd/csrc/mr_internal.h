@@ -18,11 +18,14 @@ enum StepKind { KIND_STARTUP = 0, KIND_LEAPFROG = 1, KIND_AVERAGE = 2, NKINDS = 
 constexpr int kMaxChunks = 16;
 constexpr int kChunkLens[] = {32, 36, 40};
 constexpr int kWave = 64;
-// a column-sweep tile: sweep_tile_segs segments of 64 x columns by
-// sweep_tile_rows y rows, one wavefront per segment and row (1024 columns per
-// tile in either precision: 256 x 4 in FP64, 128 x 8 in FP32)
-constexpr int sweep_tile_segs(bool fp64) { return fp64 ? 4 : 2; }
-constexpr int sweep_tile_rows(bool fp64) { return fp64 ? 4 : 8; }
+// Column-sweep tile shapes: segments of 64 x columns by rows, one wavefront
+// per segment and row.  mr_init picks one per context (mr_ctx::sweep_shape).
+struct SweepShape {
+  int segs, rows;
+};
+constexpr int kSweepShapes = 4;
+constexpr SweepShape kSweepShape[kSweepShapes] = {{4, 4}, {3, 4}, {2, 8}, {1, 16}};
+int sweep_pick_shape(int nx, bool fp64);
 
 // Grid tables of one precision (device pointers into the context's table block).
 template <typename T>
@@ -117,6 +120,7 @@ struct mr_ctx {
   mr::ZSys zf[mr::NKINDS];         // forward systems per step kind
   mr::ZSys zt[mr::NKINDS];         // transposed systems per step kind
   mr::SweepSys sw[mr::NKINDS];     // column-sweep factors per step kind
+  int sweep_shape;                 // column-sweep tile shape (index into kSweepShape)
   int sweep_pref;                  // run step sequences as column sweeps
   int sweep_single;                // run single steps as a column sweep and its back substitution
   void* sweep_e[2];                // elimination values of two consecutive sweep steps (lazy)

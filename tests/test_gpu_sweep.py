@@ -5,10 +5,12 @@ mr_scalar_step on columns taller than the line solver's) against the oracle
 Each sweep kernel finishes the previous step's implicit solve while it
 eliminates its own in the other z direction, so a sequence of count steps
 runs count + 1 kernels; a sequence of one step is a sweep and a back
-substitution.  Tiles are 256 x 4 columns in FP64 and 128 x 8 in FP32, walked
-in bands of 4 and 8 x tiles.  Cases cover ragged tiles (x and y not multiples
-of the tile, a single column), several x tiles and a last band of one tile
-(x of 1100), one to three z levels, every
+substitution.  The tile shape follows N_x (the first of each precision's
+shapes whose width divides it, else the one with the fewest idle lanes: FP64
+256 x 4, 192 x 4, 128 x 8, 64 x 16; FP32 128 x 8, 192 x 4, 256 x 4, 64 x 16),
+walked in bands of 4 (FP64) and 8 (FP32) x tiles.  Cases cover every shape,
+ragged tiles (x and y not multiples of the tile, a single column), several x
+tiles and a last band of one tile (x of 1100), one to three z levels, every
 step type, both directions of the last back substitution (odd and even
 counts), tall columns of 700 and 1024 levels, the coarse step of the temporal
 strategy, and the FP32 tier.  Tolerances as for the fused step: 1e-12 (FP64),
@@ -47,13 +49,15 @@ SIZES = [((5, 3, 7), (3, 1, 2), 1.0),     # x of 15 (one ragged tile), y of 3 (o
          ((4, 9, 2), (2, 1, 1), 0.5),     # two levels, y of 9 (tiles of 8 and 1 rows)
          ((3, 4, 3), (2, 2, 1), 2.0),     # three levels
          ((70, 17, 12), (1, 1, 2), 2.0),  # y of 17: five FP64, three FP32 row tiles; 24 levels
-         ((550, 2, 2), (2, 1, 1), 1.0)]   # x of 1100: 5 FP64 tiles (bands of 4 and 1), 9 FP32 (8 and 1)
+         ((550, 2, 2), (2, 1, 1), 1.0),   # x of 1100: 6 FP64 tiles of 192 (bands of 4 and 2), 9 FP32 of 128 (8 and 1)
+         ((96, 3, 3), (2, 2, 1), 1.0),    # x of 192: tiles of 192 x 4 in both precisions
+         ((160, 10, 3), (2, 2, 1), 1.0)]  # x of 320: tiles of 64 x 16 in both, y of 20 (16 and 4 rows)
 
 
 def _dt(nc, m):
-    """The explicit x diffusion bound at 1100 columns on the unit width is
-    below the advective step: take a small step there."""
-    return 1e-5 if nc[0] * m[0] > 1000 else None
+    """The explicit x diffusion bound at 320 columns and more on the unit
+    width is close to or below the advective step: take a small step there."""
+    return 1e-5 if nc[0] * m[0] > 300 else None
 
 
 @pytest.mark.parametrize("nc,m,gamma", SIZES)
@@ -81,7 +85,7 @@ def test_sweep_sequence_parity(nc, m, gamma, n0, count):
             assert rel_max(host(outs[q]), want[q]) <= FP64_TOL, q
 
 
-@pytest.mark.parametrize("nc,m,gamma", SIZES[:2] + SIZES[-2:])
+@pytest.mark.parametrize("nc,m,gamma", SIZES[:2] + SIZES[-4:])
 def test_sweep_single_steps_fp32(nc, m, gamma):
     """FP32 tier through the column sweeps, step by step from the oracle's own
     levels (cast): the per-step bar and the fluctuation and increment bounds."""
