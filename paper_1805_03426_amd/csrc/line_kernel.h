@@ -169,8 +169,8 @@ __device__ __forceinline__ double lane_shl(double v) {
 // shuffle); the z pair from carrying one more level.  The reverse step's
 // transposed faces also need u, v, w on the faces one beyond each side.
 template <typename T, int L, int MODE, int ROWS, int MINB, int PFD, bool WALLS, bool EXPZ, bool ORD4,
-          bool UXY = false>
-__global__ void __launch_bounds__(1024, MINB) line_kernel(LineArgs<T> A) {
+          bool UXY = false, int MT = 1024>
+__global__ void __launch_bounds__(MT, MINB) line_kernel(LineArgs<T> A) {
   static_assert(!((EXPZ || ORD4) && MODE == SEED), "the seed solve has no stencil");
   static_assert(!ORD4 || ROWS <= 2, "fourth-order faces need patches of at most two rows");
   static_assert(!UXY || !(WALLS || EXPZ || ORD4), "uniform-width kernels exist for the plain variant only");
@@ -558,29 +558,34 @@ struct StepLayout {
 // Compile-time variants: side walls, explicit z share, fourth-order faces,
 // and for the plain periodic variant uniform x and y widths (the seed solve
 // has no stencil: one variant).
-template <typename T, int LL, int MODE, int R, int MB, int PF, bool W, bool E, bool O, bool U = false>
+template <typename T, int LL, int MODE, int R, int MB, int PF, bool W, bool E, bool O, bool U = false, int MT = 1024>
 void launch_one(dim3 grid, dim3 block, hipStream_t s, const LineArgs<T>& a) {
-  hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, W, E, O, U>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((line_kernel<T, LL, MODE, R, MB, PF, W, E, O, U, MT>), grid, block, 0, s, a);
 }
 
-template <typename T, int LL, int MODE, int R, int MB, int PF, bool W>
+template <typename T, int LL, int MODE, int R, int MB, int PF, bool W, int MT>
 void launch_eo(bool expz, bool ord4, dim3 grid, dim3 block, hipStream_t s, const LineArgs<T>& a) {
   if (ord4) {
-    if (expz) launch_one<T, LL, MODE, R, MB, PF, W, true, true>(grid, block, s, a);
-    else launch_one<T, LL, MODE, R, MB, PF, W, false, true>(grid, block, s, a);
+    if (expz) launch_one<T, LL, MODE, R, MB, PF, W, true, true, false, MT>(grid, block, s, a);
+    else launch_one<T, LL, MODE, R, MB, PF, W, false, true, false, MT>(grid, block, s, a);
   } else {
-    if (expz) launch_one<T, LL, MODE, R, MB, PF, W, true, false>(grid, block, s, a);
-    else launch_one<T, LL, MODE, R, MB, PF, W, false, false>(grid, block, s, a);
+    if (expz) launch_one<T, LL, MODE, R, MB, PF, W, true, false, false, MT>(grid, block, s, a);
+    else launch_one<T, LL, MODE, R, MB, PF, W, false, false, false, MT>(grid, block, s, a);
   }
 }
 
-template <typename T, int LL, int MODE, int R, int MB, int PF>
+// MT: the largest workgroup the kernel is compiled for.  At 1024 threads (16
+// chunks) a wavefront gets at most 128 VGPRs, and the variants (side walls,
+// explicit z share, fourth-order faces, stretched x or y) spill there; columns
+// of at most 8 chunks launch them compiled for 512 threads (up to 256 VGPRs,
+// no spill).  The plain uniform-width kernels fit either way and stay at 1024.
+template <typename T, int LL, int MODE, int R, int MB, int PF, int MT>
 void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 block, hipStream_t s,
                     const LineArgs<T>& a) {
   if constexpr (MODE == SEED) {
-    launch_one<T, LL, MODE, R, MB, PF, false, false, false>(grid, block, s, a);
+    launch_one<T, LL, MODE, R, MB, PF, false, false, false, false, MT>(grid, block, s, a);
   } else {
-    if (walls) launch_eo<T, LL, MODE, R, MB, PF, true>(expz, ord4, grid, block, s, a);
+    if (walls) launch_eo<T, LL, MODE, R, MB, PF, true, MT>(expz, ord4, grid, block, s, a);
     else if (uxy && !expz && !ord4) {
       // the plain FP32 step runs two levels of loads ahead (forward with chunks
       // of up to 36 levels: 1-3% faster; reverse with chunks of 32: 1%); those
@@ -588,7 +593,7 @@ void launch_variant(bool walls, bool expz, bool ord4, bool uxy, dim3 grid, dim3 
       constexpr int PFU = (sizeof(T) == 4 && ((MODE == FWD && LL <= 36) || (MODE == BWD && LL == 32))) ? 2 : PF;
       launch_one<T, LL, MODE, R, MB, PFU, false, false, false, true>(grid, block, s, a);
     }
-    else launch_eo<T, LL, MODE, R, MB, PF, false>(expz, ord4, grid, block, s, a);
+    else launch_eo<T, LL, MODE, R, MB, PF, false, MT>(expz, ord4, grid, block, s, a);
   }
 }
 
@@ -651,7 +656,8 @@ hipError_t launch_line(mr_ctx* c, LineArgs<T> a, hipStream_t s) {
   switch (c->L) {
 #define MR_CASE(LL)                                                                             \
   case LL:                                                                                      \
-    launch_variant<T, LL, MODE, rows, mb, pf>(walls, expz, ord4, uxy, grid, block, s, a);       \
+    if (c->nch <= 8) launch_variant<T, LL, MODE, rows, mb, pf, 512>(walls, expz, ord4, uxy, grid, block, s, a); \
+    else launch_variant<T, LL, MODE, rows, mb, pf, 1024>(walls, expz, ord4, uxy, grid, block, s, a); \
     break;
     MR_CASE(32)
     MR_CASE(36)
