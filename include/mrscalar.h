@@ -97,6 +97,10 @@ typedef struct {
                               line solver (one kernel per step), 2 = column sweeps (see
                               mr_scalar_steps; x and y periodic with uniform widths, z_explicit 0,
                               face order 2 only) */
+  int32_t sweep_tile;      /* tile of the column sweeps: 0 = chosen from nx by the library,
+                              1 = 256 x 4 columns (FP64 only), 2 = 192 x 4, 3 = 128 x 8,
+                              4 = 64 x 16; results are the same for every tile (MR_EINVAL
+                              otherwise) */
 } mr_desc;
 
 /* Nusselt summary of one scalar field (Eq. 22, instantaneous). */
@@ -184,10 +188,11 @@ int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_c
  * outs[0] and th_cur, outs[q] from outs[q-1] and outs[q-2]): a ring of three
  * buffers satisfies this.  Results equal count calls of mr_scalar_step to
  * rounding.
- * With step_method 2, and with step_method 0 on grids of at least 512 x 512
- * columns or columns too tall for the line solver (x and y periodic with
- * uniform widths and the plain method in both cases), the steps run as column
- * sweeps: each kernel back-substitutes the previous step's implicit solve
+ * With step_method 2, and with step_method 0 on grids whose sweep tiles keep
+ * the GPU full (at least 16 wavefronts per CU, rounds of tiles at least 3/4
+ * full: 576 x 576 and 1024 x 1024 columns, not 256 x 256) or columns too tall
+ * for the line solver (x and y periodic with uniform widths and the plain
+ * method in both cases), the steps run as column sweeps: each kernel back-substitutes the previous step's implicit solve
  * while it eliminates its own in the other z direction, so a cell moves
  * 7 values per step instead of the 6 of one fused step but no column is held
  * whole on chip.  These sweeps use two elimination fields of the context

@@ -42,6 +42,7 @@ class mr_desc(ctypes.Structure):
         ("z_explicit", c_double),
         ("face_order", c_int32),
         ("step_method", c_int32),
+        ("sweep_tile", c_int32),
     ]
 
 

@@ -23,13 +23,14 @@ _METHOD = {"auto": 0, "line": 1, "sweep": 2}
 
 def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot="dirichlet",
               bc_top="dirichlet", precision="fp64", side_x="periodic", side_y="periodic",
-              z_explicit=0.0, face_order=2, step_method="auto"):
+              z_explicit=0.0, face_order=2, step_method="auto", sweep_tile=0):
     """Build an ``mr_desc``; returns (desc, keepalive) -- keep the second alive
     while the descriptor is in use (it owns the face arrays).  side_x / side_y:
     "periodic" or "walls" (adiabatic no-slip side walls); z_explicit: share w of
     the z diffusion taken explicit on the lagged level (0 to 1/2); face_order:
     2 (mean of the two cells) or 4 (fourth-order face values, uniform x and y);
-    step_method: "auto", "line" (fused line solver) or "sweep" (column sweeps)."""
+    step_method: "auto", "line" (fused line solver) or "sweep" (column sweeps);
+    sweep_tile: 0 (chosen from nx) or 1..4 (256 x 4, 192 x 4, 128 x 8, 64 x 16)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
     mx, my, mz = (int(a) for a in m)
     n = [f.size - 1 for f in faces]
@@ -50,6 +51,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     d.z_explicit = float(z_explicit)
     d.face_order = int(face_order)
     d.step_method = _METHOD[step_method]
+    d.sweep_tile = int(sweep_tile)
     return d, faces
 
 
@@ -104,11 +106,11 @@ class Context:
 
     def __init__(self, xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0,
                  bc_bot="dirichlet", bc_top="dirichlet", precision="fp64", side_x="periodic",
-                 side_y="periodic", z_explicit=0.0, face_order=2, step_method="auto"):
+                 side_y="periodic", z_explicit=0.0, face_order=2, step_method="auto", sweep_tile=0):
         if not torch.cuda.is_available():
             raise RuntimeError("the multiple-resolution library needs a HIP GPU")
         desc, keep = make_desc(xf, yf, zf, m, ra, pr, dt, n_avg, t_bot, t_top, bc_bot, bc_top, precision,
-                               side_x, side_y, z_explicit, face_order, step_method)
+                               side_x, side_y, z_explicit, face_order, step_method, sweep_tile)
         self.desc, self._keep = desc, keep
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._ctx = c_void_p()

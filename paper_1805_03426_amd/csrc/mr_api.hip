@@ -10,6 +10,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "mr_internal.h"
 
 namespace {
@@ -219,6 +221,8 @@ int check_desc(const mr_desc* d, Problem& P) {
   if (!(d->z_explicit >= 0.0 && d->z_explicit <= 0.5)) return MR_EINVAL;
   if (d->face_order != 0 && d->face_order != 2 && d->face_order != 4) return MR_EINVAL;
   if (d->step_method < 0 || d->step_method > 2) return MR_EINVAL;
+  if (d->sweep_tile < 0 || d->sweep_tile > mr::kSweepShapes) return MR_EINVAL;
+  if (d->sweep_tile == 1 && d->precision != MR_FP64) return MR_EINVAL;   // 256 x 4 is FP64 only
   int st;
   if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
   if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
@@ -523,7 +527,19 @@ inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 size_t elem_size(const mr_ctx* c) { return c->precision == MR_FP64 ? 8 : 4; }
 
+// A roctx range named after an entry point, around its host work and its
+// launches, so that a marker trace (rocprofv3 --marker-trace) shows each call
+// beside the kernels it enqueued.
+struct CallRange {
+  explicit CallRange(const char* name) { roctxRangePushA(name); }
+  ~CallRange() { roctxRangePop(); }
+  CallRange(const CallRange&) = delete;
+  CallRange& operator=(const CallRange&) = delete;
+};
+
 }  // namespace
+
+#define MR_CALL_RANGE() CallRange mr_call_range_(__func__)
 
 // ===================================================================== C ABI
 extern "C" {
@@ -595,6 +611,7 @@ int mr_host_z_face_weights(const mr_desc* desc, double* w_out) {
 }
 
 int mr_init(const mr_desc* desc, mr_ctx** out) {
+  MR_CALL_RANGE();
   if (!out) return MR_EINVAL;
   Problem P;
   int st = check_desc(desc, P);
@@ -711,7 +728,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
     cus = 256;
   const bool f64 = c->precision == MR_FP64;
-  c->sweep_shape = mr::sweep_pick_shape(c->nx, f64);
+  c->sweep_shape = desc->sweep_tile > 0 ? desc->sweep_tile - 1 : mr::sweep_pick_shape(c->nx, f64);
   const mr::SweepShape sh = mr::kSweepShape[c->sweep_shape];
   const int tw = 64 * sh.segs;
   const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + sh.rows - 1) / sh.rows);
@@ -747,6 +764,7 @@ int mr_destroy(mr_ctx* ctx) {
 
 int mr_interpolate_velocity(mr_ctx* ctx, const void* U, const void* V, const void* W, void* u,
                             void* v, void* w, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !U || !V || !W || !u || !v || !w) return MR_EINVAL;
   MR_LAUNCH(mr::launch_refine(ctx, U, V, W, u, v, w, as_stream(stream)));
   return MR_OK;
@@ -754,6 +772,7 @@ int mr_interpolate_velocity(mr_ctx* ctx, const void* U, const void* V, const voi
 
 int mr_interpolate_velocity_backward(mr_ctx* ctx, const void* gu, const void* gv, const void* gw,
                                      void* gU, void* gV, void* gW, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !gu || !gv || !gw || !gU || !gV || !gW) return MR_EINVAL;
   MR_LAUNCH(mr::launch_refine_transpose(ctx, gu, gv, gw, gU, gV, gW, as_stream(stream)));
   return MR_OK;
@@ -761,6 +780,7 @@ int mr_interpolate_velocity_backward(mr_ctx* ctx, const void* gu, const void* gv
 
 int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w, double* dev_out,
                   void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !u || !v || !w || !dev_out) return MR_EINVAL;
   MR_LAUNCH(mr::launch_divergence(ctx, u, v, w, dev_out, as_stream(stream)));
   return MR_OK;
@@ -768,6 +788,7 @@ int mr_divergence(mr_ctx* ctx, const void* u, const void* v, const void* w, doub
 
 int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_cur, void* th_next,
                    const void* u, const void* v, const void* w, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || n < 0 || !th_cur || !th_next || !u || !v || !w) return MR_EINVAL;
   if (n > 0 && !th_prev) return MR_EINVAL;
   if (th_next == th_cur || th_next == th_prev) return MR_EINVAL;
@@ -784,6 +805,7 @@ int mr_scalar_step(mr_ctx* ctx, int64_t n, const void* th_prev, const void* th_c
 
 int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev, const void* th_cur,
                     void* const* outs, const void* u, const void* v, const void* w, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || n0 < 0 || count < 1 || !th_cur || !outs || !u || !v || !w) return MR_EINVAL;
   if (n0 > 0 && !th_prev) return MR_EINVAL;
   const void* thp = n0 > 0 ? th_prev : th_cur;
@@ -807,6 +829,7 @@ int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev,
 }
 
 int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || n < 0 || !lam || !mu_out || lam == mu_out) return MR_EINVAL;
   if (ctx->nch == 0) return MR_ESHAPE;
   MR_LAUNCH(mr::launch_seed(ctx, n, lam, mu_out, as_stream(stream)));
@@ -816,6 +839,7 @@ int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void*
 int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const void* mu_cur,
                             const void* lam_add, void* out, const void* u, const void* v,
                             const void* w, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || n < 0 || !mu_cur || !out || !u || !v || !w) return MR_EINVAL;
   if (out == mu_cur || (mu_next && out == mu_next) || (lam_add && out == lam_add)) return MR_EINVAL;
   if (ctx->nch == 0) return MR_ESHAPE;
@@ -826,6 +850,7 @@ int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const v
 
 int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps, const void* const* thetas,
                      const void* const* mus, void* gu, void* gv, void* gw, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || count < 1 || count > 16 || !steps || !thetas || !mus || !gu || !gv || !gw)
     return MR_EINVAL;
   for (int s = 0; s < count; ++s)
@@ -836,6 +861,7 @@ int mr_velocity_grad(mr_ctx* ctx, int32_t count, const int64_t* steps, const voi
 
 int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile, mr_nu* host_out,
                void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !theta || !w || !dev_profile) return MR_EINVAL;
   hipStream_t s = as_stream(stream);
   MR_LAUNCH(mr::launch_nusselt(ctx, theta, w, dev_profile, s));
@@ -856,12 +882,14 @@ int mr_nusselt(mr_ctx* ctx, const void* theta, const void* w, double* dev_profil
 
 int mr_nusselt_noalloc(mr_ctx* ctx, const void* theta, const void* w, double* dev_profile,
                        void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !theta || !w || !dev_profile) return MR_EINVAL;
   return mr::nusselt_fixed(ctx, theta, w, dev_profile, as_stream(stream));
 }
 
 int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, double* host_out,
                            void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !theta || !dev_out) return MR_EINVAL;
   hipStream_t s = as_stream(stream);
   MR_LAUNCH(mr::launch_dissipation(ctx, theta, dev_out, s));
@@ -877,6 +905,7 @@ int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, doub
 int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, const void* W0,
                                  const void* U1, const void* V1, const void* W1, int64_t i,
                                  int64_t mt, void* u, void* v, void* w, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !U0 || !V0 || !W0 || !U1 || !V1 || !W1 || !u || !v || !w) return MR_EINVAL;
   if (mt < 1 || i < 0 || i > mt) return MR_EINVAL;
   MR_LAUNCH(mr::launch_refine_time(ctx, U0, V0, W0, U1, V1, W1, (double)i / (double)mt, u, v, w,
@@ -885,6 +914,7 @@ int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, co
 }
 
 int mr_integrate_scalar(mr_ctx* ctx, const void* theta, void* theta_c, void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || !theta || !theta_c || theta == theta_c) return MR_EINVAL;
   MR_LAUNCH(mr::launch_integrate(ctx, theta, theta_c, as_stream(stream)));
   return MR_OK;
@@ -894,6 +924,7 @@ int mr_coarse_step(mr_ctx* ctx, int64_t n0, int32_t mt, const void* U0, const vo
                    const void* W0, const void* U1, const void* V1, const void* W1, void* u, void* v,
                    void* w, void* const* ring, int32_t* prev, int32_t* cur, void* theta_c,
                    void* stream) {
+  MR_CALL_RANGE();
   if (!ctx || n0 < 0 || mt < 1 || !U0 || !V0 || !W0 || !U1 || !V1 || !W1 || !u || !v || !w)
     return MR_EINVAL;
   if (!ring || !prev || !cur) return MR_EINVAL;

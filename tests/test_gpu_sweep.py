@@ -85,6 +85,32 @@ def test_sweep_sequence_parity(nc, m, gamma, n0, count):
             assert rel_max(host(outs[q]), want[q]) <= FP64_TOL, q
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sweep_tiles_bit_identical(prec):
+    """Every tile shape gives the same bits: each column's arithmetic does not
+    depend on which lanes, rows or workgroups hold its neighbours (x of 200 and
+    y of 37 are ragged for every shape; 9 steps from n = 0 through an averaging
+    step)."""
+    print("case sweep tiles", prec, flush=True)
+    case = Case((100, 37, 12), (2, 1, 2), 1.5, kmax=1, n_avg=4, random_velocity=True, precision=prec, dt=1e-5)
+    uvw = O.refine_velocity(case.g, case.U, case.V, case.W)
+    from paper_1805_03426_amd.context import Context
+    results = {}
+    for tile in ((1, 2, 3, 4) if prec == "fp64" else (2, 3, 4)):
+        with Context(case.xf, case.yf, case.zf, case.m, case.ra, case.pr, case.dt, n_avg=case.n_avg,
+                     precision=prec, step_method="sweep", sweep_tile=tile) as ctx:
+            du = [case.d(a) for a in uvw]
+            ring = [ctx.empty(ctx.shape_cell) for _ in range(3)]
+            outs = [ring[q % 3] for q in range(9)]
+            ctx.scalar_steps(0, None, case.d(case.th0), outs, *du)
+            torch.cuda.synchronize()
+            results[tile] = [host(outs[q]) for q in (6, 7, 8)]
+    first = results[min(results)]
+    for tile, got in results.items():
+        for a, b in zip(got, first):
+            assert np.array_equal(a, b), tile
+
+
 @pytest.mark.parametrize("nc,m,gamma", SIZES[:2] + SIZES[-4:])
 def test_sweep_single_steps_fp32(nc, m, gamma):
     """FP32 tier through the column sweeps, step by step from the oracle's own

@@ -235,6 +235,14 @@ def test_unknown_step_method_rejected():
     assert _init_status(step_method=-1) == _lib.MR_EINVAL
 
 
+def test_sweep_tile_validated():
+    """The column sweeps' tile is 0 (chosen from nx) or one of four shapes;
+    256 x 4 (1) exists in FP64 only."""
+    assert _init_status(sweep_tile=5) == _lib.MR_EINVAL
+    assert _init_status(sweep_tile=-1) == _lib.MR_EINVAL
+    assert _init_status(sweep_tile=1, precision=_lib.MR_FP32) == _lib.MR_EINVAL
+
+
 def test_null_arguments_rejected():
     L = _lib.lib()
     assert L.mr_init(None, None) == _lib.MR_EINVAL
