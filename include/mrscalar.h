@@ -221,6 +221,28 @@ int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const v
                             const void* lam_add, void* out,
                             const void* u, const void* v, const void* w, void* stream);
 
+/* Reverse steps n0, n0-1, .., n0-count+1 (Eqs. 5-7 transposed, the same mu
+ * form as mr_scalar_step_backward, without lam_add), all with n >= 1, in one
+ * call: outs[q] (device, count pointers in a host array) receives
+ * mu^{n0-q-1}, what mr_scalar_step_backward returns for step n0-q.
+ * mu_next = mu^{n0+1} (NULL when there is no step n0+1), mu_cur = mu^{n0}.
+ * Every output must differ from the two levels before it (outs[0] from
+ * mu_cur and mu_next, outs[1] from outs[0] and mu_cur, outs[q] from outs[q-1]
+ * and outs[q-2]).  Results equal count calls of mr_scalar_step_backward to
+ * rounding.  Where the context runs step sequences as column sweeps
+ * (mr_get_step_method 2) the reverse steps run as column sweeps too: each
+ * kernel back-substitutes the previous reverse step's transposed solve while
+ * it eliminates its own the other way (7 values per cell and step), with the
+ * same two elimination fields; columns taller than the line solver's are then
+ * accepted.  The reverse step n = 0 (the start-up step's, whose output is the
+ * adjoint of theta^0 itself) is not part of a sequence: call
+ * mr_scalar_step_backward for it.  MR_EINVAL for count < 1, n0-count+1 < 1,
+ * NULL pointers or an output equal to one of the two levels before it;
+ * MR_ESHAPE for tall columns on the line-solver path. */
+int mr_scalar_steps_backward(mr_ctx* ctx, int64_t n0, int32_t count, const void* mu_next,
+                             const void* mu_cur, void* const* outs, const void* u, const void* v,
+                             const void* w, void* stream);
+
 /* Accumulate the dense face-velocity gradient of `count` steps (count <= 16):
  *   g_f += sum_s tau_{n_s} A_f (theta_L + theta_R)/2 (mu_R/V_R - mu_L/V_L)
  * on every dense face f with cells L and R (zero on the z walls), where

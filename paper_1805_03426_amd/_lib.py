@@ -22,7 +22,7 @@ EXPORTS = [
     "mr_velocity_grad", "mr_nusselt", "mr_copy_probe", "mr_host_refinement_table",
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
     "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
-    "mr_coarse_step", "mr_host_z_face_weights", "mr_scalar_steps", "mr_get_step_method",
+    "mr_coarse_step", "mr_host_z_face_weights", "mr_scalar_steps", "mr_scalar_steps_backward", "mr_get_step_method",
     "mr_nusselt_noalloc",
 ]
 
@@ -84,6 +84,7 @@ def lib():
         "mr_divergence": (c_int, [P, P, P, P, P, P]),
         "mr_scalar_step": (c_int, [P, c_int64, P, P, P, P, P, P, P]),
         "mr_scalar_steps": (c_int, [P, c_int64, c_int32, P, P, POINTER(c_void_p), P, P, P, P]),
+        "mr_scalar_steps_backward": (c_int, [P, c_int64, c_int32, P, P, POINTER(c_void_p), P, P, P, P]),
         "mr_adjoint_seed": (c_int, [P, c_int64, P, P, P]),
         "mr_scalar_step_backward": (c_int, [P, c_int64, P, P, P, P, P, P, P, P]),
         "mr_velocity_grad": (c_int, [P, c_int32, POINTER(c_int64), POINTER(c_void_p),

@@ -89,15 +89,23 @@ class ScalarRollout(torch.autograd.Function):
                     mr.scalar_steps(s, pprev, pcur, outs, u, v, w)
                 for n, out in zip(range(s, e - 1), outs):
                     states[n + 1] = out
-            # reverse steps e-1 .. s; mu^n is kept for the velocity gradient
-            mus = {}
-            for n in range(e - 1, s - 1, -1):
-                mus[n] = mu_cur
+            # reverse steps e-1 .. max(s, 1) as one sequence (mu^n kept for the
+            # velocity gradient), then the start-up step's reverse on its own
+            mus = {e - 1: mu_cur}
+            lo = max(s, 1)
+            if e - 1 >= lo:
+                outs = [mr.empty(mr.shape_cell) for _ in range(e - lo)]
+                mr.scalar_steps_backward(e - 1, mu_next, mu_cur, outs, u, v, w)
+                for q, out in enumerate(outs):
+                    mus[e - 2 - q] = out
+                mu_next = outs[-2] if len(outs) > 1 else mu_cur
+                mu_cur = outs[-1]
+            if s == 0:
                 out = mr.empty(mr.shape_cell)
-                mr.scalar_step_backward(n, mu_next, mu_cur, None, out, u, v, w)
-                if n == 0:
-                    g_theta0 = out
+                mr.scalar_step_backward(0, mu_next, mu_cur, None, out, u, v, w)
+                g_theta0 = out
                 mu_next, mu_cur = mu_cur, out
+            mus = {n: m for n, m in mus.items() if s <= n < e}
             # one velocity-gradient call per group of at most MAX_GRAD_STEPS steps
             for g0 in range(s, e, MAX_GRAD_STEPS):
                 idx = list(range(g0, min(g0 + MAX_GRAD_STEPS, e)))

@@ -277,6 +277,22 @@ class Context:
               self._ctx)
         return outs
 
+    def scalar_steps_backward(self, n0, mu_next, mu_cur, outs, u, v, w):
+        """Reverse steps n0 .. n0-len(outs)+1 (all >= 1): outs[q] receives
+        mu^{n0-q-1} (each output must differ from the two levels before it);
+        mu_next = mu^{n0+1} or None."""
+        k = len(outs)
+        if k < 1:
+            raise ValueError("outs must hold at least one buffer")
+        op = (c_void_p * k)(*[self._ptr(t, self.shape_cell, "outs[%d]" % q).value for q, t in enumerate(outs)])
+        args = [self._ptr(mu_next, self.shape_cell, "mu_next") if mu_next is not None else None,
+                self._ptr(mu_cur, self.shape_cell, "mu_cur"), op,
+                self._ptr(u, self.shape_cell, "u"), self._ptr(v, self.shape_cell, "v"),
+                self._ptr(w, self.shape_w, "w")]
+        check(lib().mr_scalar_steps_backward(self._ctx, c_int64(n0), c_int32(k), *args, _stream()),
+              "mr_scalar_steps_backward", self._ctx)
+        return outs
+
     @property
     def step_method(self):
         """The method step sequences run with: "line" or "sweep"."""

@@ -115,7 +115,7 @@ struct Rh {
   T u0, u1, v0, v1, wf;
 };
 
-template <typename T, int TX, int TY, bool DOWN, bool FIRST, int PF>
+template <typename T, int TX, int TY, bool DOWN, bool FIRST, int PF, bool REV>
 __global__ void __launch_bounds__(64 * TX * TY) sweep_kernel(SweepArgs<T> A) {
   static_assert(TY >= 2, "the halo rows belong to two different wavefronts");
   constexpr int W = 64 * TX;          // tile width (TX wavefronts per row)
@@ -188,11 +188,21 @@ __global__ void __launch_bounds__(64 * TX * TY) sweep_kernel(SweepArgs<T> A) {
     const T mlo = tab(A.zlo, k), mhi = tab(A.zhi, k);
     const T below = DOWN ? tnext : t2, above = DOWN ? t2 : tnext;
     const T wlo = DOWN ? q1.wf : w2, whi = DOWN ? w2 : q1.wf;
-    const T fzl = mlo * wlo * (below + q1.tc);
-    const T fzr = mhi * whi * (q1.tc + above);
-    const T adv = -half * ((q1.u1 * (q1.tc + q1.txp) - q1.u0 * (q1.txm + q1.tc)) * A.uhx +
-                           (q1.v1 * (q1.tc + q1.typ) - q1.v0 * (q1.tym + q1.tc)) * A.uhy +
-                           (fzr - fzl) * tab(A.ihz, k));
+    T adv;
+    if constexpr (REV) {
+      // C_u^T mu: each face f (cells L, R) adds u_f (mu_R/h_R - mu_L/h_L)/2 to both cells
+      const T ihzk = tab(A.ihz, k);
+      const T czl = mlo * wlo * (q1.tc * ihzk - below * tab(A.ihz, k > 0 ? k - 1 : 0));
+      const T czr = mhi * whi * (above * tab(A.ihz, k < nz - 1 ? k + 1 : nz - 1) - q1.tc * ihzk);
+      adv = half * ((q1.u0 * (q1.tc - q1.txm) + q1.u1 * (q1.txp - q1.tc)) * A.uhx +
+                    (q1.v0 * (q1.tc - q1.tym) + q1.v1 * (q1.typ - q1.tc)) * A.uhy + czl + czr);
+    } else {
+      const T fzl = mlo * wlo * (below + q1.tc);
+      const T fzr = mhi * whi * (q1.tc + above);
+      adv = -half * ((q1.u1 * (q1.tc + q1.txp) - q1.u0 * (q1.txm + q1.tc)) * A.uhx +
+                     (q1.v1 * (q1.tc + q1.typ) - q1.v0 * (q1.tym + q1.tc)) * A.uhy + (fzr - fzl) * tab(A.ihz, k));
+    }
+    // the x/y diffusion of the second field (its transpose is itself on uniform widths)
     const T lap = (q1.pxp + q1.pxm - T(2) * q1.pc) * A.uxx + (q1.pyp + q1.pym - T(2) * q1.pc) * A.uyy;
     const T rr = A.ap * q1.pc + A.ac * q1.tc + A.tau * adv + A.tk * lap;
     ecar = tab(A.em, k) * ((double)rr + tab(A.tkb, k)) + tab(A.ea, k) * ecar;
@@ -326,20 +336,34 @@ const Geom<double>& geom<double>(const mr_ctx* c) { return c->g64; }
 template <>
 const Geom<float>& geom<float>(const mr_ctx* c) { return c->g32; }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool REV>
 hipError_t launch_shape(int nx, int ny, bool first, bool down, SweepArgs<T>& a, hipStream_t s) {
   constexpr int PF = SweepTile<T>::pf;
   const int ntx = (nx + 64 * TX - 1) / (64 * TX), nty = (ny + TY - 1) / TY;
   a.band = SweepTile<T>::band < ntx ? SweepTile<T>::band : ntx;
   const dim3 grid((unsigned)(ntx * nty)), block(64, TX * TY);
   if (first) {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, true, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, true, PF>), grid, block, 0, s, a);
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, true, PF, REV>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, true, PF, REV>), grid, block, 0, s, a);
   } else {
-    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, false, PF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, false, PF>), grid, block, 0, s, a);
+    if (down) hipLaunchKernelGGL((sweep_kernel<T, TX, TY, true, false, PF, REV>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<T, TX, TY, false, false, PF, REV>), grid, block, 0, s, a);
   }
   return hipGetLastError();
+}
+
+// The launch of one sweep in the context's tile shape.
+template <typename T, bool REV>
+hipError_t launch_tiles(mr_ctx* c, bool first, bool down, SweepArgs<T>& a, hipStream_t s) {
+  switch (c->sweep_shape) {
+    case 0:
+      if constexpr (sizeof(T) == 8)
+        return launch_shape<T, kSweepShape[0].segs, kSweepShape[0].rows, REV>(c->nx, c->ny, first, down, a, s);
+      return hipErrorInvalidValue;   // not an FP32 shape
+    case 1: return launch_shape<T, kSweepShape[1].segs, kSweepShape[1].rows, REV>(c->nx, c->ny, first, down, a, s);
+    case 2: return launch_shape<T, kSweepShape[2].segs, kSweepShape[2].rows, REV>(c->nx, c->ny, first, down, a, s);
+    default: return launch_shape<T, kSweepShape[3].segs, kSweepShape[3].rows, REV>(c->nx, c->ny, first, down, a, s);
+  }
 }
 
 template <typename T>
@@ -380,20 +404,76 @@ hipError_t sweep_t(mr_ctx* c, int64_t m, bool first, bool down, const void* src,
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
-  switch (c->sweep_shape) {
-    case 0:
-      if constexpr (sizeof(T) == 8) return launch_shape<T, kSweepShape[0].segs, kSweepShape[0].rows>(c->nx, c->ny, first, down, a, s);
-      return hipErrorInvalidValue;   // not an FP32 shape
-    case 1: return launch_shape<T, kSweepShape[1].segs, kSweepShape[1].rows>(c->nx, c->ny, first, down, a, s);
-    case 2: return launch_shape<T, kSweepShape[2].segs, kSweepShape[2].rows>(c->nx, c->ny, first, down, a, s);
-    default: return launch_shape<T, kSweepShape[3].segs, kSweepShape[3].rows>(c->nx, c->ny, first, down, a, s);
-  }
+  return launch_tiles<T, false>(c, first, down, a, s);
 }
 
 template <typename T>
 hipError_t backsub_t(mr_ctx* c, int64_t m, bool down, const void* e, void* out, hipStream_t s) {
   const SweepSys& z = c->sw[step_kind(m, c->n_avg)];
   // step m was eliminated walking the other way
+  const double* cb = down ? z.up_cb : z.dn_cb;
+  const int nxy = c->nx * c->ny;
+  const dim3 grid((unsigned)((nxy + 255) / 256)), block(256);
+  if (down) hipLaunchKernelGGL((backsub_kernel<T, true>), grid, block, 0, s, (const T*)e, (T*)out, cb, nxy, c->nz);
+  else hipLaunchKernelGGL((backsub_kernel<T, false>), grid, block, 0, s, (const T*)e, (T*)out, cb, nxy, c->nz);
+  return hipGetLastError();
+}
+
+// The reverse step n as a sweep, in the adjoint's mu form: the transposed
+// stencils of step n applied to mu^n, the transposed lagged x/y diffusion of
+// step n+1 applied to mu^{n+1} (absent after the last step: zero weights),
+// then the elimination of the transposed implicit system of step n-1, whose
+// solution is mu^{n-1}.  Walking the other way, the next kernel back-
+// substitutes it.
+template <typename T>
+hipError_t sweep_bwd_t(mr_ctx* c, int64_t n, bool first, bool down, bool has_next, const void* src,
+                       const void* lag, void* mu_out, void* e_out, const void* u, const void* v, const void* w,
+                       hipStream_t s) {
+  const int kind = step_kind(n, c->n_avg);
+  const Geom<T>& g = geom<T>(c);
+  SweepArgs<T> a;
+  ::memset((void*)&a, 0, sizeof(a));
+  a.src = (const T*)src;
+  a.lag = (const T*)lag;
+  a.u = (const T*)u;
+  a.v = (const T*)v;
+  a.w = (const T*)w;
+  a.th_out = (T*)mu_out;
+  a.e_out = (T*)e_out;
+  if (!first) {
+    // the previous kernel eliminated the system of mu^n (the transpose of
+    // step n's) walking the other way
+    const SweepSys& pz = c->swt[kind];
+    a.cb = down ? pz.up_cb : pz.dn_cb;
+  }
+  const SweepSys& z = c->swt[step_kind(n - 1, c->n_avg)];
+  a.em = down ? z.dn_m : z.up_m;
+  a.ea = down ? z.dn_a : z.up_a;
+  a.tkb = z.tkb;
+  a.ihz = g.ihz;
+  a.zlo = g.zlo;
+  a.zhi = g.zhi;
+  a.ac = (T)alpha_cur(kind);
+  a.tau = (T)c->tau[kind];
+  if (has_next) {
+    const int k1 = step_kind(n + 1, c->n_avg);
+    a.ap = (T)alpha_prev(k1);
+    a.tk = (T)(c->tau[k1] * c->kappa);
+  }
+  a.uhx = (T)c->uhx;
+  a.uhy = (T)c->uhy;
+  a.uxx = (T)(c->uhx * c->uhx);
+  a.uyy = (T)(c->uhy * c->uhy);
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  return launch_tiles<T, true>(c, first, down, a, s);
+}
+
+template <typename T>
+hipError_t backsub_bwd_t(mr_ctx* c, int64_t n, bool down, const void* e, void* out, hipStream_t s) {
+  // mu^{n-1} was eliminated (transpose of step n-1) walking the other way
+  const SweepSys& z = c->swt[step_kind(n - 1, c->n_avg)];
   const double* cb = down ? z.up_cb : z.dn_cb;
   const int nxy = c->nx * c->ny;
   const dim3 grid((unsigned)((nxy + 255) / 256)), block(256);
@@ -470,6 +550,31 @@ hipError_t launch_sweep_steps(mr_ctx* c, int64_t n0, int count, const void* thp,
     if (e != hipSuccess) return e;
   }
   return launch_sweep_finish(c, n0, count, outs[count - 1], s);
+}
+
+hipError_t launch_sweep_bwd_steps(mr_ctx* c, int64_t n0, int count, const void* mu_next, const void* mu_cur,
+                                  void* const* outs, const void* u, const void* v, const void* w, hipStream_t s) {
+  hipError_t e = ensure_sweep_buffers(c);
+  if (e != hipSuccess) return e;
+  const bool f64 = c->precision == MR_FP64;
+  for (int q = 0; q < count; ++q) {
+    // reverse step n0 - q reads mu^{n0-q+1} as its second field and finishes
+    // mu^{n0-q} (q > 0); its elimination (of mu^{n0-q-1}) goes to buffer q % 2
+    const int64_t n = n0 - q;
+    const bool down = (q & 1) == 0, first = q == 0;
+    const void* src = first ? mu_cur : c->sweep_e[(q - 1) & 1];
+    const void* lag = q == 0 ? (mu_next ? mu_next : mu_cur) : (q == 1 ? mu_cur : outs[q - 2]);
+    const bool has_next = q > 0 || mu_next != nullptr;
+    void* out = first ? nullptr : outs[q - 1];
+    e = f64 ? sweep_bwd_t<double>(c, n, first, down, has_next, src, lag, out, c->sweep_e[q & 1], u, v, w, s)
+            : sweep_bwd_t<float>(c, n, first, down, has_next, src, lag, out, c->sweep_e[q & 1], u, v, w, s);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t last = n0 - count + 1;
+  const bool down = ((count - 1) & 1) != 0;
+  const void* el = c->sweep_e[(count - 1) & 1];
+  return f64 ? backsub_bwd_t<double>(c, last, down, el, outs[count - 1], s)
+             : backsub_bwd_t<float>(c, last, down, el, outs[count - 1], s);
 }
 
 }  // namespace mr

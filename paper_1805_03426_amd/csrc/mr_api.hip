@@ -632,7 +632,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
   GeomOffsets o64 = pack_geom<double>(pk, P, desc, R, idx, npad);
   GeomOffsets o32 = pack_geom<float>(pk, P, desc, R, idx, npad);
   ZOffsets zfo[mr::NKINDS], zto[mr::NKINDS];
-  SweepOffsets swo[mr::NKINDS];
+  SweepOffsets swo[mr::NKINDS], swto[mr::NKINDS];
   double taus[mr::NKINDS];
   const int nz = P.z.n;
   vector<double> sub(nz), diag(nz), sup(nz), bz(nz), tsub(nz), tsup(nz);
@@ -647,16 +647,20 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     sh.tkb.assign(nz, 0.0);
     for (int k = 0; k < nz; ++k) sh.tkb[k] = tk * bz[k];
     swo[kind] = pack_sweep(pk, sh);
-    if (nch == 0) continue;
-    ZHost zh, th;
-    if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
-    zh.tkb.assign((size_t)nch * L, 0.0);
-    for (int k = 0; k < nz; ++k) zh.tkb[k] = tk * bz[k];
     // transpose: sub^T_k = sup_{k-1}, sup^T_k = sub_{k+1}
     for (int k = 0; k < nz; ++k) {
       tsub[k] = k > 0 ? sup[k - 1] : 0.0;
       tsup[k] = k < nz - 1 ? sub[k + 1] : 0.0;
     }
+    SweepHost sht;   // the reverse steps' systems: no wall source
+    if (!sweep_factors(nz, tsub.data(), diag.data(), tsup.data(), sht)) return MR_EINVAL;
+    sht.tkb.assign(nz, 0.0);
+    swto[kind] = pack_sweep(pk, sht);
+    if (nch == 0) continue;
+    ZHost zh, th;
+    if (!z_factors(nz, L, sub.data(), diag.data(), sup.data(), zh)) return MR_EINVAL;
+    zh.tkb.assign((size_t)nch * L, 0.0);
+    for (int k = 0; k < nz; ++k) zh.tkb[k] = tk * bz[k];
     if (!z_factors(nz, L, tsub.data(), diag.data(), tsup.data(), th)) return MR_EINVAL;
     th.tkb.assign((size_t)nch * L, 0.0);
     zfo[kind] = pack_z(pk, zh);
@@ -715,6 +719,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
       c->zt[k] = z_ptrs(base, zto[k]);
     }
     c->sw[k] = sweep_ptrs(base, swo[k]);
+    c->swt[k] = sweep_ptrs(base, swto[k]);
   }
   // step sequences run as column sweeps where the line solver cannot take the
   // columns, and where the sweep's tiles keep the GPU full: at least 16
@@ -845,6 +850,30 @@ int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const v
   if (ctx->nch == 0) return MR_ESHAPE;
   MR_LAUNCH(mr::launch_step_backward(ctx, n, mu_next, mu_cur, lam_add, out, u, v, w,
                                      as_stream(stream)));
+  return MR_OK;
+}
+
+int mr_scalar_steps_backward(mr_ctx* ctx, int64_t n0, int32_t count, const void* mu_next, const void* mu_cur,
+                             void* const* outs, const void* u, const void* v, const void* w, void* stream) {
+  MR_CALL_RANGE();
+  if (!ctx || count < 1 || n0 - count + 1 < 1 || !mu_cur || !outs || !u || !v || !w) return MR_EINVAL;
+  // every output differs from the two levels before it
+  for (int32_t q = 0; q < count; ++q) {
+    const void* l1 = q >= 1 ? outs[q - 1] : mu_cur;
+    const void* l2 = q >= 2 ? outs[q - 2] : (q == 1 ? mu_cur : mu_next);
+    if (!outs[q] || outs[q] == l1 || outs[q] == l2) return MR_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  if (ctx->sweep_pref) {
+    MR_LAUNCH(mr::launch_sweep_bwd_steps(ctx, n0, count, mu_next, mu_cur, outs, u, v, w, s));
+    return MR_OK;
+  }
+  if (ctx->nch == 0) return MR_ESHAPE;
+  for (int32_t q = 0; q < count; ++q) {
+    const void* nxt = q >= 2 ? outs[q - 2] : (q == 1 ? mu_cur : mu_next);
+    const void* cur = q >= 1 ? outs[q - 1] : mu_cur;
+    MR_LAUNCH(mr::launch_step_backward(ctx, n0 - q, nxt, cur, nullptr, outs[q], u, v, w, s));
+  }
   return MR_OK;
 }
 

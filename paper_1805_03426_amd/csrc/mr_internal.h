@@ -120,6 +120,7 @@ struct mr_ctx {
   mr::ZSys zf[mr::NKINDS];         // forward systems per step kind
   mr::ZSys zt[mr::NKINDS];         // transposed systems per step kind
   mr::SweepSys sw[mr::NKINDS];     // column-sweep factors per step kind
+  mr::SweepSys swt[mr::NKINDS];    // the same for the transposed systems (reverse steps)
   int sweep_shape;                 // column-sweep tile shape (index into kSweepShape)
   int sweep_pref;                  // run step sequences as column sweeps
   int sweep_single;                // run single steps as a column sweep and its back substitution
@@ -171,6 +172,11 @@ hipError_t launch_sweep_finish(mr_ctx* c, int64_t n0, int count, void* out, hipS
 hipError_t launch_sweep_steps(mr_ctx* c, int64_t n0, int count, const void* thp, const void* thc,
                               void* const* outs, const void* u, const void* v, const void* w,
                               hipStream_t s);
+// Column-sweep reverse steps n0, n0-1, .., n0-count+1 (all >= 1): outs[q]
+// receives mu^{n0-q-1}; mu_next = mu^{n0+1} or null after the last step.
+hipError_t launch_sweep_bwd_steps(mr_ctx* c, int64_t n0, int count, const void* mu_next, const void* mu_cur,
+                                  void* const* outs, const void* u, const void* v, const void* w,
+                                  hipStream_t s);
 // Grows the context's reduction scratch to at least `bytes`.
 hipError_t ensure_red(mr_ctx* c, size_t bytes);
 // The fixed device memory of the allocation-free Nusselt entry point: looks up

@@ -86,6 +86,44 @@ def test_sweep_sequence_parity(nc, m, gamma, n0, count):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc,m,gamma", SIZES[:2] + SIZES[-3:])
+def test_reverse_sweeps_match_line_reverse_steps(nc, m, gamma, prec):
+    """Reverse-step sequences through the column sweeps (mr_scalar_steps_backward)
+    against the line solver's reverse steps one at a time, every output:
+    the last step of a rollout (no mu^{n0+1}), sequences with mu^{n0+1}
+    across the averaging steps (N_p = 3), and a single step down to mu^0.
+    FP64 within 1e-12, FP32 within 1e-5 relative L2."""
+    print("case reverse sweeps", nc, m, prec, flush=True)
+    case = Case(nc, m, gamma, kmax=1, n_avg=3, random_velocity=True, precision=prec, dt=_dt(nc, m))
+    uvw = O.refine_velocity(case.g, case.U, case.V, case.W)
+    rng = np.random.default_rng(8)
+    mus = [rng.standard_normal(case.th0.shape) for _ in range(2)]
+    for n0, count, has_next in ((6, 6, False), (5, 4, True), (1, 1, True)):
+        want = []
+        with _ctx(case, "line") as ctx:
+            du = [case.d(a) for a in uvw]
+            nxt = case.d(mus[0]) if has_next else None
+            cur = case.d(mus[1])
+            for q in range(count):
+                out = ctx.empty(ctx.shape_cell)
+                ctx.scalar_step_backward(n0 - q, nxt, cur, None, out, *du)
+                want.append(host(out))
+                nxt, cur = cur, out
+        with _ctx(case, "sweep") as ctx:
+            du = [case.d(a) for a in uvw]
+            ring = [ctx.empty(ctx.shape_cell) for _ in range(3)]
+            outs = [ring[q % 3] for q in range(count)]
+            ctx.scalar_steps_backward(n0, case.d(mus[0]) if has_next else None, case.d(mus[1]), outs, *du)
+            torch.cuda.synchronize()
+            for q in range(max(0, count - 3), count):
+                got = host(outs[q])
+                if prec == "fp64":
+                    assert rel_max(got, want[q]) <= FP64_TOL, (n0, q)
+                else:
+                    assert rel_l2(got, want[q]) <= FP32_TOL, (n0, q)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_sweep_tiles_bit_identical(prec):
     """Every tile shape gives the same bits: each column's arithmetic does not
     depend on which lanes, rows or workgroups hold its neighbours (x of 200 and
