@@ -205,7 +205,9 @@ int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev,
 /* ------------------------------------------------------------ adjoint */
 
 /* mu^n = (I - tau_n kappa Lz)^-T lam: the transposed implicit solve of step n.
- * Seeds the reverse sweep with lam = dL/dtheta^{n+1}.  mu_out must not alias lam. */
+ * Seeds the reverse sweep with lam = dL/dtheta^{n+1}.  mu_out must not alias lam.
+ * On columns taller than the line solver's, a solve column by column (its
+ * elimination values pass through mu_out). */
 int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream);
 
 /* One fused reverse step.  With mu^m = (I - tau_m kappa Lz)^-T dL/dtheta^{m+1}:
@@ -216,7 +218,9 @@ int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void*
  * n == 0: out = dL/dtheta^0 = lam^0 + tau_0 kappa Lh^T mu^0 (the start-up step
  *         reads theta^0 for its diffusion too).
  * out must not alias the inputs.  Velocity gradients are accumulated
- * separately by mr_velocity_grad. */
+ * separately by mr_velocity_grad.  On columns taller than the line solver's
+ * the step runs as a column sweep (n >= 1: a sweep and a back substitution;
+ * n = 0: one pass with no solve); lam_add is then refused (MR_ESHAPE). */
 int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const void* mu_cur,
                             const void* lam_add, void* out,
                             const void* u, const void* v, const void* w, void* stream);

@@ -56,6 +56,7 @@ struct SweepArgs {
   const T* zlo;       // 1 where level k has an interior z face below
   const T* zhi;       // 1 where level k has an interior z face above
   T ap, ac, tau, tk;  // step m: weights of theta^{m-1}, theta^m; tau; tau kappa
+  T tk0;              // reverse start-up step: tau_0 kappa on the x/y diffusion of mu^0 itself
   T uhx, uhy, uxx, uyy;
   int nx, ny, nz;
   int band;           // x tiles per band of the tile walk
@@ -204,7 +205,12 @@ __global__ void __launch_bounds__(64 * TX * TY) sweep_kernel(SweepArgs<T> A) {
     }
     // the x/y diffusion of the second field (its transpose is itself on uniform widths)
     const T lap = (q1.pxp + q1.pxm - T(2) * q1.pc) * A.uxx + (q1.pyp + q1.pym - T(2) * q1.pc) * A.uyy;
-    const T rr = A.ap * q1.pc + A.ac * q1.tc + A.tau * adv + A.tk * lap;
+    T rr = A.ap * q1.pc + A.ac * q1.tc + A.tau * adv + A.tk * lap;
+    if constexpr (REV) {
+      // the start-up step's reverse: its diffusion acts on theta^0, whose
+      // adjoint this pass forms (tk0 = 0 for every other reverse step)
+      rr += A.tk0 * ((q1.txp + q1.txm - T(2) * q1.tc) * A.uxx + (q1.typ + q1.tym - T(2) * q1.tc) * A.uyy);
+    }
     ecar = tab(A.em, k) * ((double)rr + tab(A.tkb, k)) + tab(A.ea, k) * ecar;
     if (act) st_nt(A.e_out + (size_t)k * nxy, oc, (T)ecar);
   };
@@ -299,6 +305,29 @@ __global__ void __launch_bounds__(256) backsub_kernel(const T* __restrict__ e, T
     const size_t o = (size_t)k * nxy + col;
     x = (double)__builtin_nontemporal_load(e + o) - tab(cb, k) * x;
     __builtin_nontemporal_store((T)x, out + o);
+  }
+}
+
+// The adjoint's seed solve on columns the line solver cannot hold: the
+// elimination walking up (its values stored in out), then the back
+// substitution walking down, one lane per column.
+template <typename T>
+__global__ void __launch_bounds__(256) solve_kernel(const T* __restrict__ lam, T* __restrict__ out,
+                                                   const double* __restrict__ m, const double* __restrict__ a,
+                                                   const double* __restrict__ cb, int nxy, int nz) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= nxy) return;
+  double e = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const size_t o = (size_t)k * nxy + col;
+    e = tab(m, k) * (double)lam[o] + tab(a, k) * e;
+    out[o] = (T)e;
+  }
+  double x = 0.0;
+  for (int k = nz - 1; k >= 0; --k) {
+    const size_t o = (size_t)k * nxy + col;
+    x = (double)out[o] - tab(cb, k) * x;
+    out[o] = (T)x;
   }
 }
 
@@ -446,10 +475,13 @@ hipError_t sweep_bwd_t(mr_ctx* c, int64_t n, bool first, bool down, bool has_nex
     const SweepSys& pz = c->swt[kind];
     a.cb = down ? pz.up_cb : pz.dn_cb;
   }
-  const SweepSys& z = c->swt[step_kind(n - 1, c->n_avg)];
+  // n = 0 (the start-up step's reverse): no solve, the right-hand side is
+  // the adjoint of theta^0 itself (identity factors: e_k = r_k)
+  const SweepSys& z = n > 0 ? c->swt[step_kind(n - 1, c->n_avg)] : c->swid;
   a.em = down ? z.dn_m : z.up_m;
   a.ea = down ? z.dn_a : z.up_a;
   a.tkb = z.tkb;
+  if (n == 0) a.tk0 = (T)(c->tau[kind] * c->kappa);
   a.ihz = g.ihz;
   a.zlo = g.zlo;
   a.zhi = g.zhi;
@@ -575,6 +607,28 @@ hipError_t launch_sweep_bwd_steps(mr_ctx* c, int64_t n0, int count, const void* 
   const void* el = c->sweep_e[(count - 1) & 1];
   return f64 ? backsub_bwd_t<double>(c, last, down, el, outs[count - 1], s)
              : backsub_bwd_t<float>(c, last, down, el, outs[count - 1], s);
+}
+
+hipError_t launch_sweep_bwd0(mr_ctx* c, const void* mu_next, const void* mu_cur, void* out, const void* u,
+                             const void* v, const void* w, hipStream_t s) {
+  // one pass walking down that reads mu^0 itself and writes the right-hand side
+  const void* lag = mu_next ? mu_next : mu_cur;
+  return c->precision == MR_FP64
+             ? sweep_bwd_t<double>(c, 0, true, true, mu_next != nullptr, mu_cur, lag, nullptr, out, u, v, w, s)
+             : sweep_bwd_t<float>(c, 0, true, true, mu_next != nullptr, mu_cur, lag, nullptr, out, u, v, w, s);
+}
+
+hipError_t launch_sweep_seed(mr_ctx* c, int64_t n, const void* lam, void* out, hipStream_t s) {
+  const SweepSys& z = c->swt[step_kind(n, c->n_avg)];
+  const int nxy = c->nx * c->ny;
+  const dim3 grid((unsigned)((nxy + 255) / 256)), block(256);
+  if (c->precision == MR_FP64)
+    hipLaunchKernelGGL(solve_kernel<double>, grid, block, 0, s, (const double*)lam, (double*)out, z.up_m, z.up_a,
+                       z.up_cb, nxy, c->nz);
+  else
+    hipLaunchKernelGGL(solve_kernel<float>, grid, block, 0, s, (const float*)lam, (float*)out, z.up_m, z.up_a,
+                       z.up_cb, nxy, c->nz);
+  return hipGetLastError();
 }
 
 }  // namespace mr

@@ -666,6 +666,13 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     zfo[kind] = pack_z(pk, zh);
     zto[kind] = pack_z(pk, th);
   }
+  // identity factors for the start-up step's reverse sweep (no solve)
+  SweepHost shid;
+  shid.up_m.assign(nz, 1.0); shid.dn_m.assign(nz, 1.0);
+  shid.up_a.assign(nz, 0.0); shid.dn_a.assign(nz, 0.0);
+  shid.up_cb.assign(nz, 0.0); shid.dn_cb.assign(nz, 0.0);
+  shid.tkb.assign(nz, 0.0);
+  const SweepOffsets swido = pack_sweep(pk, shid);
   vector<double> dcz(P.z.dc);
   size_t o_hx64 = pk.put(P.x.h), o_hy64 = pk.put(P.y.h), o_dcz = pk.put(dcz), o_hz64 = pk.put(P.z.h);
 
@@ -721,6 +728,7 @@ int mr_init(const mr_desc* desc, mr_ctx** out) {
     c->sw[k] = sweep_ptrs(base, swo[k]);
     c->swt[k] = sweep_ptrs(base, swto[k]);
   }
+  c->swid = sweep_ptrs(base, swido);
   // step sequences run as column sweeps where the line solver cannot take the
   // columns, and where the sweep's tiles keep the GPU full: at least 16
   // wavefronts per CU in all, and either one round of tiles (one workgroup
@@ -836,7 +844,11 @@ int mr_scalar_steps(mr_ctx* ctx, int64_t n0, int32_t count, const void* th_prev,
 int mr_adjoint_seed(mr_ctx* ctx, int64_t n, const void* lam, void* mu_out, void* stream) {
   MR_CALL_RANGE();
   if (!ctx || n < 0 || !lam || !mu_out || lam == mu_out) return MR_EINVAL;
-  if (ctx->nch == 0) return MR_ESHAPE;
+  if (ctx->nch == 0) {
+    // columns beyond the line solver: a column-by-column solve
+    MR_LAUNCH(mr::launch_sweep_seed(ctx, n, lam, mu_out, as_stream(stream)));
+    return MR_OK;
+  }
   MR_LAUNCH(mr::launch_seed(ctx, n, lam, mu_out, as_stream(stream)));
   return MR_OK;
 }
@@ -847,7 +859,19 @@ int mr_scalar_step_backward(mr_ctx* ctx, int64_t n, const void* mu_next, const v
   MR_CALL_RANGE();
   if (!ctx || n < 0 || !mu_cur || !out || !u || !v || !w) return MR_EINVAL;
   if (out == mu_cur || (mu_next && out == mu_next) || (lam_add && out == lam_add)) return MR_EINVAL;
-  if (ctx->nch == 0) return MR_ESHAPE;
+  if (ctx->nch == 0) {
+    // columns beyond the line solver: the reverse step as a column sweep
+    // and its back substitution (no lam_add there)
+    if (lam_add) return MR_ESHAPE;
+    hipStream_t s = as_stream(stream);
+    if (n == 0) {
+      MR_LAUNCH(mr::launch_sweep_bwd0(ctx, mu_next, mu_cur, out, u, v, w, s));
+    } else {
+      void* outs[1] = {out};
+      MR_LAUNCH(mr::launch_sweep_bwd_steps(ctx, n, 1, mu_next, mu_cur, outs, u, v, w, s));
+    }
+    return MR_OK;
+  }
   MR_LAUNCH(mr::launch_step_backward(ctx, n, mu_next, mu_cur, lam_add, out, u, v, w,
                                      as_stream(stream)));
   return MR_OK;

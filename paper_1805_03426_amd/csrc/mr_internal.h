@@ -121,6 +121,7 @@ struct mr_ctx {
   mr::ZSys zt[mr::NKINDS];         // transposed systems per step kind
   mr::SweepSys sw[mr::NKINDS];     // column-sweep factors per step kind
   mr::SweepSys swt[mr::NKINDS];    // the same for the transposed systems (reverse steps)
+  mr::SweepSys swid;               // identity factors (the start-up step's reverse: no solve)
   int sweep_shape;                 // column-sweep tile shape (index into kSweepShape)
   int sweep_pref;                  // run step sequences as column sweeps
   int sweep_single;                // run single steps as a column sweep and its back substitution
@@ -177,6 +178,11 @@ hipError_t launch_sweep_steps(mr_ctx* c, int64_t n0, int count, const void* thp,
 hipError_t launch_sweep_bwd_steps(mr_ctx* c, int64_t n0, int count, const void* mu_next, const void* mu_cur,
                                   void* const* outs, const void* u, const void* v, const void* w,
                                   hipStream_t s);
+// The start-up step's reverse (out = dL/dtheta^0) and the seed solve, for
+// columns the line solver cannot hold.
+hipError_t launch_sweep_bwd0(mr_ctx* c, const void* mu_next, const void* mu_cur, void* out, const void* u,
+                             const void* v, const void* w, hipStream_t s);
+hipError_t launch_sweep_seed(mr_ctx* c, int64_t n, const void* lam, void* out, hipStream_t s);
 // Grows the context's reduction scratch to at least `bytes`.
 hipError_t ensure_red(mr_ctx* c, size_t bytes);
 // The fixed device memory of the allocation-free Nusselt entry point: looks up

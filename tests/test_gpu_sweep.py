@@ -198,7 +198,8 @@ def test_sweep_sequence_fp32_matches_line_solver_to_rounding():
 def test_tall_columns_fp64(nz, gamma):
     """Columns beyond the line solver's 640 levels (1024: the paper's dense
     mesh height, Sec. 4.4) on a small x-y footprint: single steps and a
-    sequence, FP64, against the oracle; the reverse step is refused."""
+    sequence, FP64, against the oracle; a reverse step with a direct loss
+    gradient (lam_add) has no sweep form and is refused."""
     print("case tall columns", nz, flush=True)
     case = Case((3, 5, nz // 2), (3, 1, 2), gamma, kmax=1, n_avg=3, random_velocity=True, dt=2e-4)
     uvw = O.refine_velocity(case.g, case.U, case.V, case.W)
@@ -217,8 +218,29 @@ def test_tall_columns_fp64(nz, gamma):
         ctx.scalar_steps(0, None, case.d(case.th0), outs, *du)
         assert rel_max(host(outs[3]), want[3]) <= FP64_TOL
         with pytest.raises(_lib.MRError) as e:
-            ctx.adjoint_seed(3, out, ring[0])
+            ctx.scalar_step_backward(3, ring[1], ring[2], out, ring[0], *du)   # lam_add = out, into ring[0]
         assert e.value.status == _lib.MR_ESHAPE
+
+
+@pytest.mark.parametrize("nz,ckpt", [(700, 2), (1024, 3)])
+def test_tall_columns_adjoint_fp64(nz, ckpt):
+    """The checkpointed rollout's gradients on columns beyond the line solver
+    (the seed solve, the reverse steps and the start-up step's reverse as
+    column sweeps) against the oracle's discrete adjoint (FP64, 5 steps)."""
+    print("case tall columns adjoint", nz, flush=True)
+    from paper_1805_03426_amd.autograd import rollout
+    case = Case((3, 5, nz // 2), (3, 1, 2), 2.0, kmax=1, n_avg=3, ra=1e4, dt=2e-4)
+    target = inputs.theta_initial(case.zf, case.g.x.n, case.g.y.n, seed=3)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(case.g, case.p, case.th0, case.U, case.V, case.W, 5, target)
+    with _ctx(case, "auto") as ctx:
+        assert ctx.step_method == "sweep"
+        th = case.d(case.th0).requires_grad_(True)
+        U, V, W = (case.d(a).requires_grad_(True) for a in (case.U, case.V, case.W))
+        out = rollout(ctx, th, U, V, W, 5, ckpt)
+        torch.autograd.backward(out, out.detach() - case.d(target))
+        got = [host(t.grad) for t in (th, U, V, W)]
+    for a, b in zip(got, (w0, wU, wV, wW)):
+        assert rel_max(a, b) <= 1e-11
 
 
 def test_coarse_step_through_sweeps():
