@@ -3,7 +3,10 @@
 One benchmark step is one whole run of the FP64 workload
 rb1024x1024x512-m2-fp64 (coarse 512x512x256 -> dense 1024x1024x512, tanh z
 grid with clustering 2.5, Ra 1e9, Pr 7): refine the coarse velocity, check its
-divergence, then 50 scalar steps with the Nusselt profile every 10 steps.
+divergence, then 50 scalar steps with the Nusselt profile every 10 steps (the
+steps run as one sequence; theta^10 .. theta^40 go to buffers of their own and
+the five profiles are taken after it: the velocity is frozen, so nothing in
+the steps depends on them).
 This is the largest workload that fits one GPU, in the paper's precision.
 Inputs are resident in HBM before the timed region.  value = dense-cell
 updates per second over the whole job.
@@ -103,41 +106,43 @@ class Run:
         self.th0 = torch.from_numpy(d["theta0"]).to("cuda", dt_)
         c = self.ctx
         self.u, self.v, self.w_ = c.empty(c.shape_cell), c.empty(c.shape_cell), c.empty(c.shape_w)
-        # ring[0] holds theta^0; the three others rotate
-        self.ring = [self.th0] + [c.empty(c.shape_cell) for _ in range(3)]
+        # ring[0] holds theta^0; ring[1..3] rotate; ring[4..] keep the levels
+        # whose Nusselt profile is taken before the last one
+        self.nu_levels = [n for n in range(w.nu_every, w.steps + 1, w.nu_every)] if w.nu_every else []
+        kept = [n for n in self.nu_levels if n < w.steps]
+        self.kept = {n: 4 + q for q, n in enumerate(kept)}
+        self.ring = [self.th0] + [c.empty(c.shape_cell) for _ in range(3 + len(kept))]
         self.runner = c.step_runner(self.ring, self.u, self.v, self.w_)
         self.div = torch.empty(2, dtype=torch.float64, device="cuda")
-        self.nprof = max(1, w.steps // max(1, w.nu_every)) if w.nu_every else 0
+        self.nprof = max(1, len(self.nu_levels))
         self.prof = torch.empty((max(1, self.nprof), c.nz + 6), dtype=torch.float64, device="cuda")
         self.host_inputs = d
 
     def step_groups(self):
-        """Ranges [n0, n1) of steps launched back to back (between two Nusselt calls)."""
-        w = self.w
-        g = w.nu_every if w.nu_every else w.steps
-        return [(n0, min(n0 + g, w.steps)) for n0 in range(0, w.steps, g)]
+        """Ranges [n0, n1) of steps launched back to back: the whole run."""
+        return [(0, self.w.steps)]
 
     def run(self, events=None):
-        """One whole run: each range of steps between two Nusselt calls is one
+        """One whole run: refinement, divergence check, the steps as one
         mr_scalar_steps call (the library picks the fused line solver or the
-        column sweeps).  With ``events`` (a list of (start, end) event pairs,
-        one per range of ``step_groups``) it records a pair on the current
-        stream around each range's step launches."""
+        column sweeps; the levels whose Nusselt profile is taken go to buffers
+        of their own), then the Nusselt profile of each of those levels.  With
+        ``events`` (one (start, end) event pair per range of ``step_groups``)
+        it records a pair on the current stream around the step launches."""
         c, w = self.ctx, self.w
         c.interpolate_velocity(self.U, self.V, self.W, out=(self.u, self.v, self.w_))
         c.divergence(self.u, self.v, self.w_, out=self.div)
-        prev = cur = 0
-        for q, (n0, n1) in enumerate(self.step_groups()):
-            outs = [1 + n % 3 for n in range(n0, n1)]   # ring[0] holds theta^0; three buffers rotate
-            if events is not None:
-                events[q][0].record()
-            self.runner.steps(n0, prev, cur, outs)
-            if events is not None:
-                events[q][1].record()
-            prev, cur = (outs[-2] if len(outs) > 1 else cur), outs[-1]
-            if w.nu_every and n1 % w.nu_every == 0:
-                c.nusselt(self.ring[cur], self.w_, profile=self.prof[q], sync=False)
-        return self.ring[cur]
+        # outs[q] receives theta^{q+1}: a kept buffer, else one of three that
+        # rotate (each output differs from the two levels before it)
+        outs = [self.kept.get(n + 1, 1 + n % 3) for n in range(w.steps)]
+        if events is not None:
+            events[0][0].record()
+        self.runner.steps(0, 0, 0, outs)
+        if events is not None:
+            events[0][1].record()
+        for q, n in enumerate(self.nu_levels):
+            c.nusselt(self.ring[outs[n - 1]], self.w_, profile=self.prof[q], sync=False)
+        return self.ring[outs[-1]]
 
 
 def time_runs(run, k, warmup, kernel_times=None):
