@@ -50,34 +50,52 @@ __device__ __forceinline__ double shfl_down_d(double v, int off) {
 }
 
 // ------------------------------------------------------------- divergence
+// Workgroups stride over the dense rows (k, j); the 256 lanes of a workgroup
+// cover the row's x range.  The row's indices and widths are workgroup-uniform
+// (no 64-bit division per cell), and the largest relative divergence is kept
+// as a fraction (|div|, sum |flux|) compared by cross-multiplication, so that
+// a cell costs no division.
 constexpr int kDivBlocks = 2048;
+
+__device__ __forceinline__ double rtab(const double* p, int k) {
+  return ((const __attribute__((address_space(4))) double*)(p))[k];
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const T* w, const double* hx,
                                                   const double* hy, const double* hz, int nx, int ny,
                                                   int nz, int wx, int wy, double* part) {
   __shared__ double sh[2][256 / kWave];
-  const int nxy = nx * ny;
-  const int64_t cells = (int64_t)nxy * nz;
-  double mabs = 0.0, mrel = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cells;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / nxy);
-    const int ip = i == nx - 1 ? 0 : i + 1;
+  const size_t nxy = (size_t)nx * ny;
+  const int rows = ny * nz;
+  double mabs = 0.0, rnum = 0.0, rden = 1.0;   // largest |div| and largest |div| / sum |flux|
+  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int k = row / ny, j = row - k * ny;
     const int jp = j == ny - 1 ? 0 : j + 1;
-    const int c0 = k * nxy + j * nx;
-    const double ax = hy[j] * hz[k], ay = hx[i] * hz[k], az = hx[i] * hy[j];
-    // side walls: the low wall face (stored) and the high one (not stored) carry nothing
-    const double ul = wx && i == 0 ? 0.0 : (double)u[c0 + i];
-    const double ur = wx && i == nx - 1 ? 0.0 : (double)u[c0 + ip];
-    const double vl = wy && j == 0 ? 0.0 : (double)v[c0 + i];
-    const double vr = wy && j == ny - 1 ? 0.0 : (double)v[k * nxy + jp * nx + i];
-    const double wl = w[c0 + i], wr = w[c0 + nxy + i];
-    const double dv = (ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az;
-    const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
-    mabs = fmax(mabs, fabs(dv));
-    if (tot > 0.0) mrel = fmax(mrel, fabs(dv) / tot);
+    const double hyj = rtab(hy, j), hzk = rtab(hz, k);
+    const double ax = hyj * hzk;
+    const bool vl0 = wy && j == 0, vr0 = wy && j == ny - 1;
+    const size_t c0 = (size_t)k * nxy + (size_t)j * nx, cp = (size_t)k * nxy + (size_t)jp * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const int ip = i == nx - 1 ? 0 : i + 1;
+      const double hxi = hx[i];
+      const double ay = hxi * hzk, az = hxi * hyj;
+      // side walls: the low wall face (stored) and the high one (not stored) carry nothing
+      const double ul = wx && i == 0 ? 0.0 : (double)u[c0 + i];
+      const double ur = wx && i == nx - 1 ? 0.0 : (double)u[c0 + ip];
+      const double vl = vl0 ? 0.0 : (double)v[c0 + i];
+      const double vr = vr0 ? 0.0 : (double)v[cp + i];
+      const double wl = w[c0 + i], wr = w[c0 + nxy + i];
+      const double dv = fabs((ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az);
+      const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
+      mabs = fmax(mabs, dv);
+      if (tot > 0.0 && dv * rden > rnum * tot) {
+        rnum = dv;
+        rden = tot;
+      }
+    }
   }
+  double mrel = rnum / rden;
   for (int off = kWave / 2; off > 0; off >>= 1) {
     mabs = fmax(mabs, shfl_down_d(mabs, off));
     mrel = fmax(mrel, shfl_down_d(mrel, off));
