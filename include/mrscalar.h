@@ -92,7 +92,8 @@ typedef struct {
   int32_t face_order;      /* face value of the advected scalar: 2 (or 0) = mean of the two cells,
                               4 = fourth order (Sec. 2.2; the polynomial whose means over the
                               two cells on each side of the face equal their values, only the
-                              cells that exist next to a wall); 4 needs uniform x and y widths */
+                              cells that exist next to a wall; on any widths in x, y and z:
+                              per-face weight tables, mr_host_face_weights) */
   int32_t step_method;     /* how step sequences run: 0 = chosen by the library, 1 = the fused
                               line solver (one kernel per step), 2 = column sweeps (see
                               mr_scalar_steps; x and y periodic with uniform widths, z_explicit 0,
@@ -361,6 +362,16 @@ int mr_host_z_system(const mr_desc* desc, int64_t n, double* sub, double* diag, 
  * weights for the cells f-2, f-1, f, f+1 (zero for the wall faces and for
  * cells beyond a wall). */
 int mr_host_z_face_weights(const mr_desc* desc, double* w_out);
+
+/* Host-only: the fourth-order face weights of one axis (0 = x, 1 = y, 2 = z;
+ * Sec. 2.2) that the step and the velocity gradient use with face_order 4:
+ * w_out receives (n+1)*4 doubles for the axis's n dense cells, face f's
+ * weights for the cells f-2, f-1, f, f+1.  A walled axis (z always) has zero
+ * rows for its wall faces and zero weights for cells beyond a wall; on a
+ * periodic axis the stencil wraps around (face f is the one between cells f-1
+ * and f, face 0 between cell n-1 and cell 0) and row n repeats row 0.
+ * MR_EINVAL for another axis. */
+int mr_host_face_weights(const mr_desc* desc, int32_t axis, double* w_out);
 
 /* The method mr_scalar_steps uses on this context: 1 = the fused line
  * solver, 2 = column sweeps. */

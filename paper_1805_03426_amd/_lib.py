@@ -22,7 +22,8 @@ EXPORTS = [
     "mr_velocity_grad", "mr_nusselt", "mr_copy_probe", "mr_host_refinement_table",
     "mr_host_z_system", "mr_get_dims", "mr_status_string", "mr_last_hip_error",
     "mr_thermal_dissipation", "mr_interpolate_velocity_time", "mr_integrate_scalar",
-    "mr_coarse_step", "mr_host_z_face_weights", "mr_scalar_steps", "mr_scalar_steps_backward", "mr_get_step_method",
+    "mr_coarse_step", "mr_host_z_face_weights", "mr_host_face_weights", "mr_scalar_steps",
+    "mr_scalar_steps_backward", "mr_get_step_method",
     "mr_nusselt_noalloc",
 ]
 
@@ -103,6 +104,7 @@ def lib():
                                      POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double)]),
         "mr_host_z_face_weights": (c_int, [POINTER(mr_desc), POINTER(c_double)]),
+        "mr_host_face_weights": (c_int, [POINTER(mr_desc), c_int32, POINTER(c_double)]),
         "mr_get_dims": (c_int, [P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                 POINTER(c_int32)]),
         "mr_get_step_method": (c_int, [P, POINTER(c_int32)]),

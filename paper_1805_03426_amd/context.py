@@ -89,6 +89,17 @@ def host_z_face_weights(desc):
     return w
 
 
+def host_face_weights(desc, axis):
+    """(n+1, 4) fourth-order face weights of one axis (0 = x, 1 = y, 2 = z),
+    face f's for the cells f-2..f+1 (wrapped on a periodic axis), as the step
+    uses them with face_order 4 (host only)."""
+    n = (desc.ncx * desc.mx, desc.ncy * desc.my, desc.ncz * desc.mz)[axis]
+    w = np.zeros((n + 1, 4))
+    check(lib().mr_host_face_weights(byref(desc), axis, w.ctypes.data_as(ctypes.POINTER(c_double))),
+          "mr_host_face_weights")
+    return w
+
+
 def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 

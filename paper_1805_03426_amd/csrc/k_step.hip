@@ -138,7 +138,8 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
   const int im2 = wx ? max(i - 2, 0) : (i - 2 + 2 * nx) % nx, ip = wx ? min(i + 1, nx - 1) : (i + 1) % nx;
   const int jm2 = wy ? max(j - 2, 0) : (j - 2 + 2 * ny) % ny, jp = wy ? min(j + 1, ny - 1) : (j + 1) % ny;
   const int km2 = max(k - 2, 0), kp = min(k + 1, nz - 1);
-  const line::W4<T> wxf = line::face_w4<T>(i, nx, wx), wyf = line::face_w4<T>(j, ny, wy);
+  line::W4<T> wxf{}, wyf{};
+  if constexpr (ORD4) wxf = line::face_w4<T>(A.g.c4x, i, nx, wx), wyf = line::face_w4<T>(A.g.c4y, j, ny, wy);
   const T* cz = A.g.c4z + 4 * k;
   T su = T(0), sv = T(0), sw = T(0);
   for (int s = 0; s < A.count; ++s) {

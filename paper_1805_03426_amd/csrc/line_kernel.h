@@ -69,28 +69,22 @@ struct Lvl {
   T w2;                     // reverse step: w on the face two levels up
 };
 
-// Weights of the fourth-order face value on face f of a uniformly spaced axis
-// of n cells, for the cells f-2, f-1, f, f+1 (Sec. 2.2: the face value of the
-// polynomial whose means over the stencil cells equal their values).  Two cells
-// on each side give (-1, 7, 7, -1)/12; on a walled axis a face next to a wall
-// cell uses the three cells that exist, (2, 5, -1)/6 or (-1, 5, 2)/6, and a
-// two-cell axis the mean.  Wall faces carry no velocity, so their weights
-// never matter.
+// Weights of the fourth-order face value on face f of an axis of n cells, for
+// the cells f-2, f-1, f, f+1, read from the axis's table (Sec. 2.2: the face
+// value of the polynomial whose means over the stencil cells equal their
+// values; on a uniform axis (-1, 7, 7, -1)/12 away from walls).  f runs from
+// -1 to n+1: a periodic axis wraps it, a walled one clamps it to a wall face,
+// whose row is zero (wall faces and faces beyond them carry no velocity).
 template <typename T>
 struct W4 {
   T a, b, c, d;
 };
 
 template <typename T>
-__device__ __forceinline__ W4<T> face_w4(int f, int n, bool walled) {
-  const bool lo = walled && f == 1, hi = walled && f == n - 1;
-  const T q = T(1.0 / 12.0), s = T(1.0 / 6.0), t = T(1.0 / 3.0), h = T(0.5);
-  W4<T> r;
-  r.a = lo ? T(0) : (hi ? -s : -q);
-  r.b = lo ? (hi ? h : t) : (hi ? T(5.0 / 6.0) : T(7.0 / 12.0));
-  r.c = hi ? (lo ? h : t) : (lo ? T(5.0 / 6.0) : T(7.0 / 12.0));
-  r.d = hi ? T(0) : (lo ? -s : -q);
-  return r;
+__device__ __forceinline__ W4<T> face_w4(const T* tab, int f, int n, bool walled) {
+  const int r = walled ? min(max(f, 0), n) : (f % n + n) % n;
+  const T* p = tab + 4 * r;
+  return W4<T>{p[0], p[1], p[2], p[3]};
 }
 
 // Load from a wave-uniform base at a 32-bit byte offset (scalar base + vector
@@ -160,9 +154,8 @@ __device__ __forceinline__ double lane_shl(double v) {
 // one more load per level, which is the next level's centre value (reused
 // there instead of loaded again), and the level below is carried.
 //
-// ORD4: fourth-order face values of the advected field on uniformly spaced x
-// and y (weights from face_w4) and on the stretched z levels (per-face weight
-// table).  The stencil field is then needed two cells away on every axis: the
+// ORD4: fourth-order face values of the advected field, with per-face weight
+// tables on every axis (face_w4 for x and y, held per lane for the column).  The stencil field is then needed two cells away on every axis: the
 // x pair comes from two lane shifts, with the first two and last two columns
 // of a row loading theirs in one more edge load; the y pair from one more halo
 // load (two rows per patch: the other row's halo value by a cross-lane
@@ -235,10 +228,15 @@ __global__ void __launch_bounds__(MT, MINB) line_kernel(LineArgs<T> A) {
   const unsigned ohalo2 = hrow == 0 ? oym2 : oyp2;             // ROWS = 2: two rows out
   const unsigned oedge_u = xfirst ? oxm : (xlast ? oxp2 : oc); // reverse: u on face i-1 / i+2
   const unsigned ohalo_v = hrow == 0 ? oym : oyp2;             // reverse, ROWS = 2: v on face j-1 / j+2
-  const W4<T> wxl = face_w4<T>(i, nx, wx), wxh = face_w4<T>(i + 1, nx, wx);
-  const W4<T> wxa = face_w4<T>(i - 1, nx, wx), wxd = face_w4<T>(i + 2, nx, wx);
-  const W4<T> wyl = face_w4<T>(j, ny, wy), wyh = face_w4<T>(j + 1, ny, wy);
-  const W4<T> wya = face_w4<T>(j - 1, ny, wy), wyd = face_w4<T>(j + 2, ny, wy);
+  W4<T> wxl{}, wxh{}, wxa{}, wxd{}, wyl{}, wyh{}, wya{}, wyd{};
+  if constexpr (ORD4) {
+    wxl = face_w4<T>(g.c4x, i, nx, wx); wxh = face_w4<T>(g.c4x, i + 1, nx, wx);
+    wyl = face_w4<T>(g.c4y, j, ny, wy); wyh = face_w4<T>(g.c4y, j + 1, ny, wy);
+    if constexpr (MODE != FWD) {
+      wxa = face_w4<T>(g.c4x, i - 1, nx, wx); wxd = face_w4<T>(g.c4x, i + 2, nx, wx);
+      wya = face_w4<T>(g.c4y, j - 1, ny, wy); wyd = face_w4<T>(g.c4y, j + 2, ny, wy);
+    }
+  }
   // reverse: faces i-1 / i+2 (j-1 / j+2) that are walls or beyond carry no velocity
   const bool zum = wx && i <= 1, zup2 = wx && i + 2 >= nx;
   const bool zvm = wy && j <= 1, zvp2 = wy && j + 2 >= ny;

@@ -62,22 +62,35 @@ bool uniform_axis(const Axis& ax) {
   return true;
 }
 
-// Fourth-order face weights of a walled axis (Sec. 2.2): face f (0 < f < n)
-// takes the two cells on each side that exist, cells lo..hi.  The face value
-// of the polynomial whose cell means equal the cell values is the derivative
-// at the face of the polynomial that interpolates the primitive
+// Fourth-order face weights of an axis (Sec. 2.2): the stencil of face f is
+// the two cells on each side of it, cells f-2..f+1.  On a walled axis only the
+// cells that exist take part (three next to a wall cell, two when the axis has
+// two cells) and the wall faces get zero rows; on a periodic axis the stencil
+// wraps around, the cells beyond an end taking the period added to (or
+// subtracted from) their coordinates, and face n repeats face 0.  The face
+// value of the polynomial whose cell means equal the cell values is the
+// derivative at the face of the polynomial that interpolates the primitive
 // P(e_j) = sum_{s<j} h_s theta_s at the stencil's edges e_0..e_m, so cell s
 // gets h_s * sum_{j>s} L_j'(x_f), L_j the Lagrange basis on the edges.
-// Returns (n+1)*4 weights, face f's for cells f-2..f+1 (zero rows for walls).
+// Returns (n+1)*4 weights, face f's for the cells f-2..f+1 in that order.
 vector<double> face_weights4(const Axis& ax) {
   const int n = ax.n;
+  const double len = ax.f[n] - ax.f[0];
+  // left edge of stencil cell c (beyond the ends of a periodic axis: the
+  // edge of the cell it wraps to, shifted by whole periods)
+  auto edge = [&](int c) {
+    if (c >= 0 && c <= n) return ax.f[c];
+    const int r = ((c % n) + n) % n;
+    return ax.f[r] + (double)((c - r) / n) * len;
+  };
   vector<double> w((size_t)(n + 1) * 4, 0.0);
-  for (int f = 1; f < n; ++f) {
-    const int lo = std::max(f - 2, 0), hi = std::min(f + 1, n - 1);
+  for (int f = ax.periodic ? 0 : 1; f < n; ++f) {
+    int lo = f - 2, hi = f + 1;
+    if (!ax.periodic) lo = std::max(lo, 0), hi = std::min(hi, n - 1);
     const int m = hi - lo + 1;
     const double xf = ax.f[f], sc = ax.h[f];
     double e[5];
-    for (int q = 0; q <= m; ++q) e[q] = (ax.f[lo + q] - xf) / sc;
+    for (int q = 0; q <= m; ++q) e[q] = (edge(lo + q) - xf) / sc;
     double dl[5];   // L_j'(0)
     for (int jj = 0; jj <= m; ++jj) {
       double sum = 0.0;
@@ -96,6 +109,8 @@ vector<double> face_weights4(const Axis& ax) {
       w[(size_t)f * 4 + (lo + q - (f - 2))] = (e[q + 1] - e[q]) * acc;
     }
   }
+  if (ax.periodic)
+    for (int q = 0; q < 4; ++q) w[(size_t)n * 4 + q] = w[q];
   return w;
 }
 
@@ -227,8 +242,6 @@ int check_desc(const mr_desc* d, Problem& P) {
   if ((st = build_axis(d->xf, (int)nx, d->mx, d->side_x == MR_PERIODIC, P.x)) != MR_OK) return st;
   if ((st = build_axis(d->yf, (int)ny, d->my, d->side_y == MR_PERIODIC, P.y)) != MR_OK) return st;
   if ((st = build_axis(d->zf, (int)nz, d->mz, false, P.z)) != MR_OK) return st;
-  // fourth-order faces: the kernels use the uniform-width weights in x and y
-  if (d->face_order == 4 && (!uniform_axis(P.x) || !uniform_axis(P.y))) return MR_EINVAL;
   P.kappa = 1.0 / sqrt(d->ra * d->pr);
   // explicit x/y diffusion: the leapfrog step is forward Euler over 2 dt
   const double hxm = *std::min_element(P.x.h.begin(), P.x.h.end());
@@ -387,7 +400,7 @@ vector<double> inv(const vector<double>& v) {
 
 struct GeomOffsets {
   size_t hx, ihx, idxc, hy, ihy, idyc, hz, ihz, iHX, iHY, Rx, Ry, Rz, sx, sy, sz, zlo, zhi;
-  size_t lzl, lzd, lzh, lztl, lzth, c4z, c4zt;
+  size_t lzl, lzd, lzh, lztl, lzth, c4z, c4zt, c4x, c4y;
 };
 
 template <typename T>
@@ -457,6 +470,8 @@ GeomOffsets pack_geom(Packer& pk, const Problem& P, const mr_desc* d, const vect
     }
   o.c4z = pk.put(cast<T>(c4));
   o.c4zt = pk.put(cast<T>(c4t));
+  o.c4x = pk.put(cast<T>(face_weights4(P.x)));
+  o.c4y = pk.put(cast<T>(face_weights4(P.y)));
   return o;
 }
 
@@ -473,6 +488,7 @@ mr::Geom<T> geom_ptrs(char* base, const GeomOffsets& o) {
   g.lzl = (const T*)(base + o.lzl); g.lzd = (const T*)(base + o.lzd); g.lzh = (const T*)(base + o.lzh);
   g.lztl = (const T*)(base + o.lztl); g.lzth = (const T*)(base + o.lzth);
   g.c4z = (const T*)(base + o.c4z); g.c4zt = (const T*)(base + o.c4zt);
+  g.c4x = (const T*)(base + o.c4x); g.c4y = (const T*)(base + o.c4y);
   return g;
 }
 
@@ -606,6 +622,16 @@ int mr_host_z_face_weights(const mr_desc* desc, double* w_out) {
   if (st != MR_OK) return st;
   if (!w_out) return MR_EINVAL;
   const vector<double> w = face_weights4(P.z);
+  memcpy(w_out, w.data(), w.size() * sizeof(double));
+  return MR_OK;
+}
+
+int mr_host_face_weights(const mr_desc* desc, int32_t axis, double* w_out) {
+  Problem P;
+  int st = check_desc(desc, P);
+  if (st != MR_OK) return st;
+  if (!w_out || axis < 0 || axis > 2) return MR_EINVAL;
+  const vector<double> w = face_weights4(axis == 0 ? P.x : (axis == 1 ? P.y : P.z));
   memcpy(w_out, w.data(), w.size() * sizeof(double));
   return MR_OK;
 }

@@ -62,6 +62,11 @@ struct Geom {
   // c4zt[4 k + s] is cell k's weight in face k-1+s ([nch*L][4], the transpose)
   const T* c4z;
   const T* c4zt;
+  // fourth-order face values in x and y: c4x[4 f + s] weights face f's value
+  // on the cells f-2+s (wrapped on a periodic axis), [nx+1][4]; zero rows for
+  // the wall faces of a walled axis, and face nx repeats face 0 on a periodic one
+  const T* c4x;
+  const T* c4y;
 };
 
 // Factors of one tridiagonal system (I - tau kappa Lz or its transpose) for

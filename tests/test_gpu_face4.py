@@ -1,6 +1,6 @@
 """GPU parity of the step with fourth-order face values of the advected scalar
-(uniform x and y, stretched z), forward and reverse, against the oracle
-through the C ABI."""
+(uniform or stretched x and y, stretched z), forward and reverse, against the
+oracle through the C ABI."""
 import dataclasses
 
 import numpy as np
@@ -18,11 +18,21 @@ SIDES = [(True, False), (False, True), (True, True)]
 
 
 class Case4(WallCase):
-    """WallCase with uniform y widths (fourth-order faces need uniform x and y)."""
+    """WallCase with fourth-order faces: uniform x and y widths, or with
+    stretched=True wall-clustered x on a walled axis (random widths on a
+    periodic one) and random y widths."""
 
-    def __init__(self, nc, m, walls, z_explicit=0.0, **kw):
+    def __init__(self, nc, m, walls, z_explicit=0.0, stretched=False, **kw):
         super().__init__(nc, m, walls, **kw)
-        self.yf = inputs.uniform_faces(self.g.y.n)
+        if stretched:
+            nx = self.g.x.n
+            if walls[0]:
+                self.xf = inputs.tanh_faces(nx, 1.2)
+            else:
+                hx = self.rng.uniform(0.6, 1.5, nx)
+                self.xf = np.concatenate([[0.0], np.cumsum(hx)]) / hx.sum()
+        else:
+            self.yf = inputs.uniform_faces(self.g.y.n)
         self.g = O.Grid(self.xf, self.yf, self.zf, m, periodic=(not walls[0], not walls[1], False))
         self.z_explicit = z_explicit
         self.p = dataclasses.replace(self.p, face_order=4, z_explicit=z_explicit)
@@ -52,6 +62,67 @@ def _steps(c, nsteps, tol):
             if c.precision == "fp64":
                 assert rel_max(got, want) <= tol, n
             prev, cur = cur, want
+
+
+def _adjoint_vs_oracle(c, N):
+    walls = c.walls
+    U, V, W = c.coarse_velocity()
+    th0 = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.1, seed=2)
+    target = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.1, seed=3)
+    _, w0, wU, wV, wW = O.rollout_loss_grad(c.g, c.p, th0, U, V, W, N, target)
+    Ul, Vl = c.to_lib(U, V)
+    with c.ctx() as ctx:
+        u, v, w = ctx.interpolate_velocity(c.d(Ul), c.d(Vl), c.d(W))
+        th = [c.d(th0)]
+        for n in range(N):
+            out = ctx.empty(ctx.shape_cell)
+            ctx.scalar_step(n, th[n - 1] if n else th[0], th[n], out, u, v, w)
+            th.append(out)
+        mu = [None] * (N + 1)
+        mu[N - 1] = ctx.empty(ctx.shape_cell)
+        ctx.adjoint_seed(N - 1, th[N] - c.d(target), mu[N - 1])
+        g0 = ctx.empty(ctx.shape_cell)
+        for n in range(N - 1, -1, -1):
+            out = ctx.empty(ctx.shape_cell) if n > 0 else g0
+            ctx.scalar_step_backward(n, mu[n + 1], mu[n], None, out, u, v, w)
+            if n > 0:
+                mu[n - 1] = out
+        gu, gv, gw = torch.zeros_like(u), torch.zeros_like(v), torch.zeros_like(w)
+        ctx.velocity_grad(list(range(N)), th[:N], mu[:N], gu, gv, gw)
+        gU, gV, gW = (host(t) for t in ctx.interpolate_velocity_backward(gu, gv, gw))
+        g0 = host(g0)
+    assert rel_max(g0, w0) <= 1e-11
+    assert rel_max(gW, wW) <= 1e-11
+    if walls[0]:
+        assert rel_max(gU[:, :, 1:], wU[:, :, 1:-1]) <= 1e-11
+    else:
+        assert rel_max(gU, wU) <= 1e-11
+    if walls[1]:
+        assert rel_max(gV[:, 1:], wV[:, 1:-1]) <= 1e-11
+    else:
+        assert rel_max(gV, wV) <= 1e-11
+
+
+def _velocity_grad_vs_oracle(c, walls):
+    th = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.2, seed=4)
+    mu = c.rng.standard_normal(th.shape)
+    n = 2
+    tau = O.step_kind(n, c.n_avg, c.dt)[0]
+    gu_o, gv_o, gw_o = O.scalar._advection_velocity_transpose(c.g, mu, th, 4)
+    with c.ctx() as ctx:
+        gu = torch.zeros(ctx.shape_cell, dtype=torch.float64, device="cuda")
+        gv, gw = torch.zeros_like(gu), torch.zeros(ctx.shape_w, dtype=torch.float64, device="cuda")
+        ctx.velocity_grad([n], [c.d(th)], [c.d(mu)], gu, gv, gw)
+        gu, gv, gw = host(gu), host(gv), host(gw)
+    want_u = tau * gu_o[:, :, :-1] if walls[0] else tau * gu_o
+    want_v = tau * gv_o[:, :-1] if walls[1] else tau * gv_o
+    if walls[0]:
+        assert np.all(gu[:, :, 0] == 0)
+    if walls[1]:
+        assert np.all(gv[:, 0] == 0)
+    assert rel_max(gu, want_u) <= FP64_TOL
+    assert rel_max(gv, want_v) <= FP64_TOL
+    assert rel_max(gw, tau * gw_o) <= FP64_TOL
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -113,60 +184,49 @@ def test_adjoint_parity_face4(walls, wz):
     oracle's discrete adjoint with fourth-order faces."""
     print("case face4 adjoint", walls, wz, flush=True)
     c = Case4((6, 5, 9), (2, 2, 2), walls, z_explicit=wz, n_avg=3, gamma=1.5)
-    U, V, W = c.coarse_velocity()
-    th0 = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.1, seed=2)
-    target = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.1, seed=3)
-    N = 7
-    _, w0, wU, wV, wW = O.rollout_loss_grad(c.g, c.p, th0, U, V, W, N, target)
-    Ul, Vl = c.to_lib(U, V)
-    with c.ctx() as ctx:
-        u, v, w = ctx.interpolate_velocity(c.d(Ul), c.d(Vl), c.d(W))
-        th = [c.d(th0)]
-        for n in range(N):
-            out = ctx.empty(ctx.shape_cell)
-            ctx.scalar_step(n, th[n - 1] if n else th[0], th[n], out, u, v, w)
-            th.append(out)
-        mu = [None] * (N + 1)
-        mu[N - 1] = ctx.empty(ctx.shape_cell)
-        ctx.adjoint_seed(N - 1, th[N] - c.d(target), mu[N - 1])
-        g0 = ctx.empty(ctx.shape_cell)
-        for n in range(N - 1, -1, -1):
-            out = ctx.empty(ctx.shape_cell) if n > 0 else g0
-            ctx.scalar_step_backward(n, mu[n + 1], mu[n], None, out, u, v, w)
-            if n > 0:
-                mu[n - 1] = out
-        gu, gv, gw = torch.zeros_like(u), torch.zeros_like(v), torch.zeros_like(w)
-        ctx.velocity_grad(list(range(N)), th[:N], mu[:N], gu, gv, gw)
-        gU, gV, gW = (host(t) for t in ctx.interpolate_velocity_backward(gu, gv, gw))
-        g0 = host(g0)
-    assert rel_max(g0, w0) <= 1e-11
-    assert rel_max(gW, wW) <= 1e-11
-    if walls[0]:
-        assert rel_max(gU[:, :, 1:], wU[:, :, 1:-1]) <= 1e-11
-    else:
-        assert rel_max(gU, wU) <= 1e-11
-    if walls[1]:
-        assert rel_max(gV[:, 1:], wV[:, 1:-1]) <= 1e-11
-    else:
-        assert rel_max(gV, wV) <= 1e-11
+    _adjoint_vs_oracle(c, 7)
 
 
 def test_velocity_grad_face4_matches_oracle():
     """The dense-face gradient of one step alone (no refinement in between)."""
     print("case face4 velocity gradient", flush=True)
     c = Case4((9, 6, 7), (2, 2, 2), (True, False), n_avg=3)
-    th = inputs.theta_initial(c.zf, c.g.x.n, c.g.y.n, noise=0.2, seed=4)
-    mu = c.rng.standard_normal(th.shape)
-    n = 2
-    tau = O.step_kind(n, c.n_avg, c.dt)[0]
-    gu_o, gv_o, gw_o = O.scalar._advection_velocity_transpose(c.g, mu, th, 4)
-    with c.ctx() as ctx:
-        gu = torch.zeros(ctx.shape_cell, dtype=torch.float64, device="cuda")
-        gv, gw = torch.zeros_like(gu), torch.zeros(ctx.shape_w, dtype=torch.float64, device="cuda")
-        ctx.velocity_grad([n], [c.d(th)], [c.d(mu)], gu, gv, gw)
-        gu, gv, gw = host(gu), host(gv), host(gw)
-    want_u = tau * gu_o[:, :, :-1]
-    assert np.all(gu[:, :, 0] == 0)
-    assert rel_max(gu, want_u) <= FP64_TOL
-    assert rel_max(gv, tau * gv_o) <= FP64_TOL
-    assert rel_max(gw, tau * gw_o) <= FP64_TOL
+    _velocity_grad_vs_oracle(c, (True, False))
+
+STRETCHED_SIDES = [PERIODIC, (True, True), (True, False), (False, True)]
+
+
+@pytest.mark.parametrize("walls", STRETCHED_SIDES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_parity_face4_stretched_xy(walls, prec):
+    """Stretched x and y (wall-clustered x beside walls, random widths
+    otherwise): the per-face weight tables of both axes, every step type."""
+    print("case face4 stretched xy", walls, prec, flush=True)
+    c = Case4((35, 9, 12), (2, 1, 2), walls, stretched=True, precision=prec, n_avg=3, dt=2e-4, gamma=1.5)
+    _steps(c, 5, FP64_TOL if prec == "fp64" else FP32_TOL)
+
+
+@pytest.mark.parametrize("nc,walls", [((3, 2, 3), PERIODIC), ((1, 3, 3), PERIODIC), ((3, 4, 3), (True, True))])
+def test_step_parity_face4_stretched_short_axes(nc, walls):
+    """Stretched axes shorter than the stencil: a periodic stencil that wraps
+    onto itself with the period added, and walled axes of three and four cells."""
+    print("case face4 stretched short axes", nc, walls, flush=True)
+    c = Case4(nc, (1, 1, 1), walls, stretched=True, n_avg=2, dt=2e-4)
+    _steps(c, 3, FP64_TOL)
+
+
+@pytest.mark.parametrize("walls,wz", [(PERIODIC, 0.0), ((True, True), 0.0), ((True, False), 0.5)])
+def test_adjoint_parity_face4_stretched(walls, wz):
+    """Reverse sweep through refine + 7 steps on stretched x and y against the
+    oracle's discrete adjoint (the transposed faces use the weights of the
+    faces one beyond each side)."""
+    print("case face4 stretched adjoint", walls, wz, flush=True)
+    c = Case4((6, 5, 9), (2, 2, 2), walls, z_explicit=wz, stretched=True, n_avg=3, gamma=1.5, dt=5e-4)
+    _adjoint_vs_oracle(c, 7)
+
+
+def test_velocity_grad_face4_stretched_matches_oracle():
+    print("case face4 stretched velocity gradient", flush=True)
+    for walls in [(True, False), (False, True), PERIODIC]:
+        c = Case4((9, 6, 7), (2, 2, 2), walls, stretched=True, n_avg=3, dt=5e-4)
+        _velocity_grad_vs_oracle(c, walls)

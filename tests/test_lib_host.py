@@ -10,7 +10,8 @@ import pytest
 
 import oracle as O
 from paper_1805_03426_amd import _lib, inputs
-from paper_1805_03426_amd.context import host_refinement_table, host_z_face_weights, host_z_system, make_desc
+from paper_1805_03426_amd.context import (host_face_weights, host_refinement_table, host_z_face_weights,
+                                           host_z_system, make_desc)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mrscalar.h")
@@ -136,16 +137,58 @@ def test_face_order_accepted(order):
     host_z_system(d, 0)
 
 
-def test_face_order4_needs_uniform_x_and_y():
+def _random_faces(rng, n):
+    h = rng.uniform(0.6, 1.5, n)
+    return np.concatenate([[0.0], np.cumsum(h)]) / h.sum()
+
+
+@pytest.mark.parametrize("walls,n", [((False, False), (12, 15)), ((False, False), (1, 2)), ((False, False), (3, 2)),
+                                     ((True, True), (12, 15)), ((True, True), (3, 4)), ((True, False), (5, 1)),
+                                     ((False, True), (2, 6))])
+def test_host_face_weights_xy_match_oracle(walls, n):
+    """Fourth-order face weights of stretched x and y axes, periodic (wrapped,
+    also on axes shorter than the stencil) and walled, against the oracle's
+    moment solve; the z axis through the same call equals mr_host_z_face_weights."""
+    rng = np.random.default_rng(5)
+    nx, ny = n
+    xf = inputs.tanh_faces(nx, 1.5) if walls[0] else _random_faces(rng, nx)
+    yf = _random_faces(rng, ny)
+    zf = inputs.tanh_faces(8, 1.5)
+    d, keep = make_desc(xf, yf, zf, (1, 1, 2), ra=1e6, pr=4.38, dt=1e-5, face_order=4,
+                        side_x="walls" if walls[0] else "periodic", side_y="walls" if walls[1] else "periodic")
+    g = O.Grid(xf, yf, zf, (1, 1, 2), periodic=(not walls[0], not walls[1], False))
+    for axis, ax in ((0, g.x), (1, g.y)):
+        got = host_face_weights(d, axis)
+        cells, wts = O.scalar.face_weights(ax, 4)
+        assert got.shape == (ax.n + 1, 4)
+        # the oracle packs a walled stencil from slot 0 and names its cells; the
+        # library's slot s is cell f-2+s (wrapped on a periodic axis)
+        want = np.zeros((ax.n + 1, 4))
+        for f in range(wts.shape[0]):
+            for s_ in range(4):
+                if wts[f, s_] != 0.0:
+                    slot = s_ if ax.periodic else cells[f, s_] - (f - 2)
+                    if ax.periodic:
+                        assert cells[f, s_] == (f - 2 + s_) % ax.n
+                    want[f, slot] += wts[f, s_]
+        if ax.periodic:
+            want[ax.n] = want[0]
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(host_face_weights(d, 2), host_z_face_weights(d))
+    buf = np.zeros(64)
+    for axis in (-1, 3):
+        assert _lib.lib().mr_host_face_weights(ctypes.byref(d), axis,
+                                               buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == _lib.MR_EINVAL
+
+
+def test_face_order4_takes_stretched_x_and_y():
     rng = np.random.default_rng(3)
-    hy = rng.uniform(0.8, 1.2, 15)
-    yf = np.concatenate([[0.0], np.cumsum(hy)]) / hy.sum()
-    xf = inputs.uniform_faces(12)
-    d, keep = make_desc(xf, yf, inputs.tanh_faces(14, 1.5), (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3, face_order=4)
-    with pytest.raises(_lib.MRError):
+    yf = _random_faces(rng, 15)
+    xf = inputs.tanh_faces(12, 1.5)
+    for order in (2, 4):
+        d, keep = make_desc(xf, yf, inputs.tanh_faces(14, 1.5), (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3,
+                            face_order=order, side_x="walls")
         host_z_system(d, 0)
-    d, keep = make_desc(xf, yf, inputs.tanh_faces(14, 1.5), (2, 3, 2), ra=1e6, pr=4.38, dt=1e-3, face_order=2)
-    host_z_system(d, 0)
 
 
 def _init_status(**over):
