@@ -45,23 +45,39 @@ hipError_t scratch_init(int device) {
 
 namespace {
 
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 __device__ __forceinline__ double shfl_down_d(double v, int off) {
   return __shfl_down(v, off, kWave);
 }
 
 // ------------------------------------------------------------- divergence
 // Workgroups stride over the dense rows (k, j); the 256 lanes of a workgroup
-// cover the row's x range.  The row's indices and widths are workgroup-uniform
-// (no 64-bit division per cell), and the largest relative divergence is kept
-// as a fraction (|div|, sum |flux|) compared by cross-multiplication, so that
-// a cell costs no division.
+// cover the row's x range, V consecutive cells a lane (16-byte vector loads
+// where V divides nx and the fields are 16-byte aligned).  The row's indices
+// and widths are workgroup-uniform (no 64-bit division per cell), and the
+// largest relative divergence is kept as a fraction (|div|, sum |flux|)
+// compared by cross-multiplication, so that a cell costs no division.
 constexpr int kDivBlocks = 2048;
 
 __device__ __forceinline__ double rtab(const double* p, int k) {
   return ((const __attribute__((address_space(4))) double*)(p))[k];
 }
 
-template <typename T>
+// V consecutive values from p (16-byte aligned when V > 1).
+template <typename T, int V>
+__device__ __forceinline__ void ldv(const T* p, T* o) {
+  if constexpr (V == 1) {
+    o[0] = *p;
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const vt x = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int q = 0; q < V; ++q) o[q] = x[q];
+  }
+}
+
+template <typename T, int V>
 __global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const T* w, const double* hx,
                                                   const double* hy, const double* hz, int nx, int ny,
                                                   int nz, int wx, int wy, double* part) {
@@ -76,22 +92,32 @@ __global__ void __launch_bounds__(256) div_kernel(const T* u, const T* v, const 
     const double ax = hyj * hzk;
     const bool vl0 = wy && j == 0, vr0 = wy && j == ny - 1;
     const size_t c0 = (size_t)k * nxy + (size_t)j * nx, cp = (size_t)k * nxy + (size_t)jp * nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-      const int ip = i == nx - 1 ? 0 : i + 1;
-      const double hxi = hx[i];
-      const double ay = hxi * hzk, az = hxi * hyj;
-      // side walls: the low wall face (stored) and the high one (not stored) carry nothing
-      const double ul = wx && i == 0 ? 0.0 : (double)u[c0 + i];
-      const double ur = wx && i == nx - 1 ? 0.0 : (double)u[c0 + ip];
-      const double vl = vl0 ? 0.0 : (double)v[c0 + i];
-      const double vr = vr0 ? 0.0 : (double)v[cp + i];
-      const double wl = w[c0 + i], wr = w[c0 + nxy + i];
-      const double dv = fabs((ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az);
-      const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
-      mabs = fmax(mabs, dv);
-      if (tot > 0.0 && dv * rden > rnum * tot) {
-        rnum = dv;
-        rden = tot;
+    for (int i0 = threadIdx.x * V; i0 < nx; i0 += blockDim.x * V) {
+      T uu[V + 1], vl_[V], vr_[V], wl_[V], wr_[V];
+      ldv<T, V>(u + c0 + i0, uu);
+      uu[V] = u[c0 + (i0 + V == nx ? 0 : i0 + V)];
+      ldv<T, V>(v + c0 + i0, vl_);
+      ldv<T, V>(v + cp + i0, vr_);
+      ldv<T, V>(w + c0 + i0, wl_);
+      ldv<T, V>(w + c0 + nxy + i0, wr_);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const int i = i0 + q;
+        const double hxi = hx[i];
+        const double ay = hxi * hzk, az = hxi * hyj;
+        // side walls: the low wall face (stored) and the high one (not stored) carry nothing
+        const double ul = wx && i == 0 ? 0.0 : (double)uu[q];
+        const double ur = wx && i == nx - 1 ? 0.0 : (double)uu[q + 1];
+        const double vl = vl0 ? 0.0 : (double)vl_[q];
+        const double vr = vr0 ? 0.0 : (double)vr_[q];
+        const double wl = wl_[q], wr = wr_[q];
+        const double dv = fabs((ur - ul) * ax + (vr - vl) * ay + (wr - wl) * az);
+        const double tot = (fabs(ul) + fabs(ur)) * ax + (fabs(vl) + fabs(vr)) * ay + (fabs(wl) + fabs(wr)) * az;
+        mabs = fmax(mabs, dv);
+        if (tot > 0.0 && dv * rden > rnum * tot) {
+          rnum = dv;
+          rden = tot;
+        }
       }
     }
   }
@@ -134,12 +160,15 @@ __global__ void __launch_bounds__(kWave) max_final(const double* part, int n, do
 
 // ---------------------------------------------------------------- Nusselt
 // partials[(k*P + p)*6 + {conv s,c, grad s,c, mean s,c}].  Block (p, q) covers
-// the horizontal range p of faces kNuFaces*q .. kNuFaces*q + kNuFaces-1: each
-// lane walks those faces for its cells carrying theta of the level below, so a
-// level is read once per group of faces instead of once per face.
+// the horizontal range p of faces kNuFaces*q .. kNuFaces*q + kNuFaces-1, V
+// consecutive cells of one row a lane (16-byte vector loads where V divides
+// nx and the fields are 16-byte aligned; the row index is one division per V
+// cells).  Each lane walks the group's faces for its cells carrying theta of
+// the level below, so a level is read once per group of faces instead of once
+// per face.
 constexpr int kNuFaces = 2;   // timed: 2 faces per group beat 1, 3, 4, 8 and 16
 
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const double* hx,
                                                   const double* hy, int nx, int ny, int nz, int P,
                                                   int dir_bot, int dir_top, double t_bot,
@@ -148,30 +177,49 @@ __global__ void __launch_bounds__(256) nu_partial(const T* th, const T* w, const
   const int kf0 = blockIdx.y * kNuFaces;   // first face of the group (faces 0..nz)
   const int p = blockIdx.x;
   const int nxy = nx * ny;
-  const int per = (nxy + P - 1) / P;
+  const int per = ((nxy + P - 1) / P + V - 1) / V * V;   // whole vectors (V divides nx)
   const int lo = p * per, hi = min(nxy, lo + per);
   DD conv[kNuFaces], grad[kNuFaces], mean[kNuFaces];
 #pragma unroll
   for (int f = 0; f < kNuFaces; ++f) conv[f] = grad[f] = mean[f] = DD{0.0, 0.0};
-  for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-    const int i = e % nx, j = e / nx;
-    const double area = hx[i] * hy[j];
-    double below = kf0 > 0 && kf0 <= nz ? (double)th[(size_t)(kf0 - 1) * nxy + e] : 0.0;
+  for (int e0 = lo + threadIdx.x * V; e0 < hi; e0 += blockDim.x * V) {
+    const int j = e0 / nx, i0 = e0 - j * nx;
+    const double hyj = hy[j];
+    double area[V], below[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      area[q] = hx[i0 + q] * hyj;
+      below[q] = 0.0;
+    }
+    if (kf0 > 0 && kf0 <= nz) {
+      T b[V];
+      ldv<T, V>(th + (size_t)(kf0 - 1) * nxy + e0, b);
+#pragma unroll
+      for (int q = 0; q < V; ++q) below[q] = (double)b[q];
+    }
 #pragma unroll
     for (int f = 0; f < kNuFaces; ++f) {
       const int k = kf0 + f;
       if (k > nz) break;
-      const double cur = k < nz ? (double)th[(size_t)k * nxy + e] : 0.0;
-      if (k > 0 && k < nz) {
-        conv[f] = dd_add(conv[f], (double)w[(size_t)k * nxy + e] * (0.5 * (below + cur)) * area);
-        grad[f] = dd_add(grad[f], (cur - below) * area);
-      } else if (k == 0) {
-        if (dir_bot) grad[f] = dd_add(grad[f], (cur - t_bot) * area);
-      } else {
-        if (dir_top) grad[f] = dd_add(grad[f], (t_top - below) * area);
+      T ct[V], wt[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) ct[q] = wt[q] = T(0);
+      if (k < nz) ldv<T, V>(th + (size_t)k * nxy + e0, ct);
+      if (k > 0 && k < nz) ldv<T, V>(w + (size_t)k * nxy + e0, wt);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const double cur = (double)ct[q];
+        if (k > 0 && k < nz) {
+          conv[f] = dd_add(conv[f], (double)wt[q] * (0.5 * (below[q] + cur)) * area[q]);
+          grad[f] = dd_add(grad[f], (cur - below[q]) * area[q]);
+        } else if (k == 0) {
+          if (dir_bot) grad[f] = dd_add(grad[f], (cur - t_bot) * area[q]);
+        } else {
+          if (dir_top) grad[f] = dd_add(grad[f], (t_top - below[q]) * area[q]);
+        }
+        if (k < nz) mean[f] = dd_add(mean[f], cur * area[q]);
+        below[q] = cur;
       }
-      if (k < nz) mean[f] = dd_add(mean[f], cur * area);
-      below = cur;
     }
   }
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -268,6 +316,13 @@ __global__ void __launch_bounds__(256) copy_kernel(const int4* __restrict__ src,
     dst[t] = src[t];
 }
 
+// Vector width of the Nusselt partials (16-byte loads where it divides nx) and
+// the number of horizontal parts (about 4096 cells each, at most kNuMaxParts).
+int nu_vec(const mr_ctx* c) {
+  const int v = c->precision == MR_FP64 ? 2 : 4;
+  return c->nx % v == 0 ? v : 1;
+}
+
 int nu_parts(const mr_ctx* c) {
   const int64_t nxy = (int64_t)c->nx * c->ny;
   int64_t P = (nxy + 256 * 16 - 1) / (256 * 16);
@@ -277,14 +332,19 @@ int nu_parts(const mr_ctx* c) {
 // The two Nusselt kernels with the partials in `part`.
 void nusselt_kernels(mr_ctx* c, const void* th, const void* w, double* prof, double* part, int P,
                      hipStream_t s) {
-  const dim3 grid(P, (c->nz + 1 + kNuFaces - 1) / kNuFaces);
+  const dim3 grid(P, (c->nz + 1 + kNuFaces - 1) / kNuFaces), block(256);
   const int db = c->bc_bot == MR_DIRICHLET, dtp = c->bc_top == MR_DIRICHLET;
-  if (c->precision == MR_FP64)
-    hipLaunchKernelGGL(nu_partial<double>, grid, dim3(256), 0, s, (const double*)th, (const double*)w,
-                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
-  else
-    hipLaunchKernelGGL(nu_partial<float>, grid, dim3(256), 0, s, (const float*)th, (const float*)w,
-                       c->hx64, c->areaw, c->nx, c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
+  // unaligned fields: one cell a lane, the same parts
+  const bool vec = aligned16(th) && aligned16(w) && nu_vec(c) > 1;
+  if (c->precision == MR_FP64) {
+    auto k = vec ? nu_partial<double, 2> : nu_partial<double, 1>;
+    hipLaunchKernelGGL(k, grid, block, 0, s, (const double*)th, (const double*)w, c->hx64, c->areaw, c->nx,
+                       c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
+  } else {
+    auto k = vec ? nu_partial<float, 4> : nu_partial<float, 1>;
+    hipLaunchKernelGGL(k, grid, block, 0, s, (const float*)th, (const float*)w, c->hx64, c->areaw, c->nx,
+                       c->ny, c->nz, P, db, dtp, c->t_bot, c->t_top, part);
+  }
   hipLaunchKernelGGL(nu_final, dim3(1), dim3(256), 0, s, (const double*)part, P, c->nz, c->dcz,
                      c->hz64, c->atot, sqrt(c->ra * c->pr), prof);
 }
@@ -307,14 +367,16 @@ hipError_t launch_divergence(mr_ctx* c, const void* u, const void* v, const void
   const int nb = (int)std::min<int64_t>(kDivBlocks, (cells + 255) / 256);
   hipError_t e = ensure_red(c, sizeof(double) * 2 * kDivBlocks);
   if (e != hipSuccess) return e;
-  if (c->precision == MR_FP64)
-    hipLaunchKernelGGL(div_kernel<double>, dim3(nb), dim3(256), 0, s, (const double*)u, (const double*)v,
-                       (const double*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy,
-                       c->red);
-  else
-    hipLaunchKernelGGL(div_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)u, (const float*)v,
-                       (const float*)w, c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy,
-                       c->red);
+  const bool vec = aligned16(u) && aligned16(v) && aligned16(w);
+  if (c->precision == MR_FP64) {
+    auto k = vec && c->nx % 2 == 0 ? div_kernel<double, 2> : div_kernel<double, 1>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, (const double*)u, (const double*)v, (const double*)w,
+                       c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy, c->red);
+  } else {
+    auto k = vec && c->nx % 4 == 0 ? div_kernel<float, 4> : div_kernel<float, 1>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, (const float*)u, (const float*)v, (const float*)w,
+                       c->hx64, c->areaw, c->hz64, c->nx, c->ny, c->nz, c->wx, c->wy, c->red);
+  }
   hipLaunchKernelGGL(max_final, dim3(1), dim3(kWave), 0, s, (const double*)c->red, nb, out);
   return hipGetLastError();
 }
