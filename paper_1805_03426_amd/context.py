@@ -28,7 +28,7 @@ def make_desc(xf, yf, zf, m, ra, pr, dt, n_avg=50, t_bot=1.0, t_top=0.0, bc_bot=
     while the descriptor is in use (it owns the face arrays).  side_x / side_y:
     "periodic" or "walls" (adiabatic no-slip side walls); z_explicit: share w of
     the z diffusion taken explicit on the lagged level (0 to 1/2); face_order:
-    2 (mean of the two cells) or 4 (fourth-order face values, uniform x and y);
+    2 (mean of the two cells) or 4 (fourth-order face values, any widths);
     step_method: "auto", "line" (fused line solver) or "sweep" (column sweeps);
     sweep_tile: 0 (chosen from nx) or 1..4 (256 x 4, 192 x 4, 128 x 8, 64 x 16)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
