@@ -187,7 +187,9 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs<T> A) {
 // Timed at 1024x1024x512 against 16 rows (one workgroup of 139 KB of LDS per
 // CU): 8 rows, two workgroups per CU, were 7% faster in FP64 and level in FP32.
 constexpr int kGradRows = 8;    // wavefronts (rows of 64 columns) per workgroup
-constexpr int kGradRun = 8;     // FP32: segments per workgroup
+// FP32 runs of 2 segments: 14.2 ms per call of 10 steps at 1024x1024x512,
+// against 14.6 ms for 4 and 15.3 ms for 8 (more workgroups, shorter walks).
+constexpr int kGradRun = 2;     // FP32: segments per workgroup
 constexpr int kGradWaves = 4;   // wavefronts per SIMD to fit (128 VGPRs)
 
 template <typename T, int KM, int ZS, bool CARRY>
@@ -319,9 +321,9 @@ __global__ void __launch_bounds__(64 * kGradRows, kGradWaves) grad_seg(GradArgs<
   }
 }
 
-// Segments of 8 levels in FP32 (runs of up to 8 segments, the level below
+// Segments of 8 levels in FP32 (runs of up to kGradRun segments, the level below
 // carried), of 4 in FP64 (no carry: its registers would not fit beside the
-// accumulators at 1024 threads per workgroup).
+// accumulators at 4 wavefronts per SIMD).
 template <typename T, int KM>
 void launch_grad_seg(mr_ctx* c, const GradArgs<T>& a, hipStream_t s) {
   constexpr bool f64 = sizeof(T) == 8;
