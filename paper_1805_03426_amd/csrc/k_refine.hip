@@ -337,9 +337,11 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
   const int col = t % kFuseCols, grp = t / kFuseCols;
   const int Ix = I0 + col / mx, sub = col - (col / mx) * mx;
   const bool xon = col < CX && Ix < ncx;
+  // (M_x = 1: R = [0 1 0] on the centred stencil, whose table entries wrap
+  // even on a walled axis; the halo column of the cell itself is Ix - I0 + 1)
   int xloc[3];
   for (int r = 0; r < 3; ++r) {
-    const int p = xon ? g.sx[Ix * 3 + r] - (I0 - 1) : 0;
+    const int p = !xon ? 0 : (mx == 1 ? Ix - I0 + r : g.sx[Ix * 3 + r] - (I0 - 1));
     xloc[r] = A.wx ? p : wrapm(p, ncx);
   }
 
@@ -381,7 +383,8 @@ __global__ void __launch_bounds__(256) refine_fused(RefArgs<T> A, int TI, int TJ
       const int m = rest % mz, jt = rest / mz;
       T u0[3], u1[3], w0[3], w1[3];
       // first stencil row of tile row jt (centred unless next to a y wall)
-      const int rs = A.wy ? g.sy[(J0 + jt) * 3] - (J0 - 1) : jt;
+      // (M_y = 1: the centred rows, as for M_x = 1 above)
+      const int rs = A.wy && my > 1 ? g.sy[(J0 + jt) * 3] - (J0 - 1) : jt;
       for (int r = 0; r < 3; ++r) {
         u0[r] = Uz[(m * NYH + rs + r) * NXH + l];
         u1[r] = Uz[(m * NYH + rs + r) * NXH + l + 1];

@@ -136,6 +136,26 @@ def test_refine_parity_with_walls_tile_edges(nc, m):
         assert rel_max(a, b) <= FP64_TOL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc,m,walls", [((35, 9, 4), (2, 1, 2), (True, True)), ((35, 10, 4), (2, 1, 2), (False, True)),
+                                        ((40, 7, 3), (1, 2, 2), (True, False)), ((40, 7, 3), (1, 1, 2), (True, False))])
+def test_refine_parity_with_walls_unit_factor(nc, m, walls, prec):
+    """A walled axis refined by 1 (R = [0 1 0] on the centred stencil, whose
+    table entries wrap even beside a wall) in the fused kernel: M_y = 1 with y
+    walls (a ragged last tile of rows), M_x = 1 with x walls (one-row tiles)."""
+    print("case walls refine unit factor", nc, m, walls, prec, flush=True)
+    c = WallCase(nc, m, walls, precision=prec)
+    U, V, W = c.coarse_velocity()
+    want = O.refine_velocity(c.g, U, V, W)
+    Ul, Vl = c.to_lib(U, V)
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    with c.ctx() as ctx:
+        got = [host(t) for t in ctx.interpolate_velocity(c.d(Ul), c.d(Vl), c.d(W))]
+    gu, gv = c.to_oracle(got[0], got[1])
+    for a, b in zip((gu, gv, got[2]), want):
+        assert rel_max(a, b) <= tol
+
+
 def _stream_field(c):
     """Coarse velocity of psi(x, z) = sin(pi x) sin(pi z) (no flow through the
     x walls or the plates; divergence-free by Stokes), oracle layout."""
