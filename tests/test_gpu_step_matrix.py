@@ -63,3 +63,30 @@ def test_step_matrix(walls, order, wz, stretched, prec):
             if prec == "fp64":
                 assert rel_max(got, want) <= tol, n
             prev, cur = cur, want
+
+
+class SmallOptCase(OptCase):
+    """The same options on a grid small enough for the oracle's discrete adjoint."""
+
+    def __init__(self, walls, order, wz, stretched):
+        WallCase.__init__(self, (6, 5, 9), (2, 2, 2), walls, n_avg=3, gamma=1.5, dt=5e-4)
+        if not stretched:
+            self.yf = inputs.uniform_faces(self.g.y.n)
+        elif walls[0]:
+            self.xf = inputs.tanh_faces(self.g.x.n, 1.2)
+        self.g = O.Grid(self.xf, self.yf, self.zf, self.m, periodic=(not walls[0], not walls[1], False))
+        self.order, self.wz = order, wz
+        self.p = dataclasses.replace(self.p, face_order=order, z_explicit=wz)
+
+
+@pytest.mark.parametrize("stretched", [False, True])
+@pytest.mark.parametrize("wz", [0.0, 0.5])
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("walls", SIDES)
+def test_adjoint_matrix(walls, order, wz, stretched):
+    """Refine + 7 steps and the hand-written reverse sweep (seed, reverse steps,
+    velocity gradient, transposed refinement) against the oracle's discrete
+    adjoint, FP64, every combination of the options."""
+    from tests.test_gpu_face4 import _adjoint_vs_oracle
+    print("case adjoint matrix", walls, order, wz, stretched, flush=True)
+    _adjoint_vs_oracle(SmallOptCase(walls, order, wz, stretched), 7)
