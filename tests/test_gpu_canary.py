@@ -6,8 +6,8 @@ output overwrites a canary, and an output element that is never written keeps
 its NaN.  Ragged sizes (x not a multiple of 64, odd y rows, z not a multiple of
 the line solver's chunk), both precisions, the fused line solver and the column
 sweeps, the variant kernels (side walls, fourth-order faces, explicit z share),
-and views that start 16-byte aligned or one element off it (the reductions
-then take their one-cell-a-lane paths)."""
+columns taller than the line solver's, and views that start 16-byte aligned or
+one element off it (the reductions then take their one-cell-a-lane paths)."""
 import numpy as np
 import pytest
 import torch
@@ -97,6 +97,18 @@ def _run(c, ctx, offset):
     ctx.interpolate_velocity_backward(gu, gv, gw, out=(gU, gV, gW))
     for t, name in ((gU, "g_U"), (gV, "g_V"), (gW, "g_W")):
         finite(t, name)
+    # the time-blended refinement and a coarse step of M_t = 2
+    U1, V1, W1 = (g.view(x.shape, dt, 0.5 * x) for x in (U, V, W))
+    ut, vt, wt = g.view(ctx.shape_cell, dt), g.view(ctx.shape_cell, dt), g.view(ctx.shape_w, dt)
+    ctx.interpolate_velocity_time(U, V, W, U1, V1, W1, 1, 3, out=(ut, vt, wt))
+    for t, name in ((ut, "u(t)"), (vt, "v(t)"), (wt, "w(t)")):
+        finite(t, name)
+    ring = [g.view(ctx.shape_cell, dt, th0), g.view(ctx.shape_cell, dt), g.view(ctx.shape_cell, dt)]
+    tcs = g.view(ctx.shape_coarse, dt)
+    prev, cur = ctx.coarse_step(0, 2, U, V, W, U1, V1, W1, (ut, vt, wt), ring, 0, 0, tcs)
+    finite(ring[prev], "coarse step theta^1")
+    finite(ring[cur], "coarse step theta^2")
+    finite(tcs, "coarse step coarse theta")
     g.check()
 
 
@@ -127,3 +139,14 @@ def test_canaries_variants(prec, offset):
                  side_y="walls", face_order=4, z_explicit=0.5) as ctx:
         assert ctx.step_method == "line"
         _run(c, ctx, offset)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_canaries_tall_columns(prec):
+    """700 levels: beyond the line solver, so the steps, the reverse steps, the
+    start-up step's reverse and the seed run as column sweeps and column solves."""
+    print("case canaries tall", prec, flush=True)
+    c = Case((32, 4, 350), (2, 2, 2), 2.0, kmax=1, n_avg=3, precision=prec, dt=1e-5)
+    with c.ctx() as ctx:
+        assert ctx.step_method == "sweep"
+        _run(c, ctx, 64)
