@@ -1067,12 +1067,25 @@ size_t fused_lds(int TI, int TJ, int mx, int my, int mz) {
 }
 
 // The time interpolation of the coarse velocity (Eq. 21, read as the linear
-// interpolation (1 - s) level0 + s level1 between the two coarse levels),
-// one coarse field.
+// interpolation (1 - s) level0 + s level1 between the two coarse levels) of
+// U, V and W in one launch: n cells of U and V, nw of W.
 template <typename T>
-__global__ void __launch_bounds__(256) blend_kernel(const T* a, const T* b, T s, T* out, int64_t n) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-    out[q] = (T(1) - s) * a[q] + s * b[q];
+struct BlendArgs {
+  const T* a[3];
+  const T* b[3];
+  T* out[3];
+  int64_t n, nw;
+  T s;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) blend_kernel(BlendArgs<T> A) {
+  const int64_t tot = 2 * A.n + A.nw;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+    const int f = q < A.n ? 0 : (q < 2 * A.n ? 1 : 2);
+    const int64_t e = q - f * A.n;
+    A.out[f][e] = (T(1) - A.s) * A.a[f][e] + A.s * A.b[f][e];
+  }
 }
 
 // U1/V1/W1 null: refine (U, V, W); otherwise refine (1 - frac) (U, V, W) + frac (U1, V1, W1),
@@ -1117,11 +1130,15 @@ hipError_t refine_t(mr_ctx* c, const Geom<T>& g, const void* U, const void* V, c
     T* Ub = (T*)c->interp_tmp;
     T* Vb = Ub + ncl;
     T* Wb = Vb + ncl;
-    const T sw = (T)frac;
-    const unsigned nbk = (unsigned)std::min<int64_t>(4096, (ncw + 255) / 256);
-    hipLaunchKernelGGL(blend_kernel<T>, dim3(nbk), dim3(256), 0, s, (const T*)U, (const T*)U1, sw, Ub, ncl);
-    hipLaunchKernelGGL(blend_kernel<T>, dim3(nbk), dim3(256), 0, s, (const T*)V, (const T*)V1, sw, Vb, ncl);
-    hipLaunchKernelGGL(blend_kernel<T>, dim3(nbk), dim3(256), 0, s, (const T*)W, (const T*)W1, sw, Wb, ncw);
+    BlendArgs<T> b;
+    b.a[0] = (const T*)U; b.a[1] = (const T*)V; b.a[2] = (const T*)W;
+    b.b[0] = (const T*)U1; b.b[1] = (const T*)V1; b.b[2] = (const T*)W1;
+    b.out[0] = Ub; b.out[1] = Vb; b.out[2] = Wb;
+    b.n = ncl;
+    b.nw = ncw;
+    b.s = (T)frac;
+    const unsigned nbk = (unsigned)std::min<int64_t>(8192, (nbl + 255) / 256);
+    hipLaunchKernelGGL(blend_kernel<T>, dim3(nbk), dim3(256), 0, s, b);
     U = Ub; V = Vb; W = Wb;
   }
   if (TJ >= 1) {
