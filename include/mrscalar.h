@@ -36,7 +36,10 @@
  * Streams: every call enqueues its kernels on the given hipStream_t (passed as
  * void*, NULL = the null stream) and returns without waiting, except
  * mr_nusselt with a non-NULL host_out, which waits for that stream.
- * A context must not be used from two host threads at once.
+ * A context must not be used from two host threads at once, and calls on one
+ * context must not overlap on different streams: the context's work buffers
+ * (reduction partials, the sweeps' elimination fields, the blended coarse
+ * velocity and the refinement intermediates) are shared by its calls.
  *
  * Errors: every function returns an int status (mr_status).  Arguments are
  * checked on the host before anything is launched; a failed HIP call returns
@@ -305,8 +308,8 @@ int mr_thermal_dissipation(mr_ctx* ctx, const void* theta, double* dev_out, doub
 /* Coarse velocity at fraction s = i/mt of a coarse step, refined to the dense
  * faces (temporal strategy, Sec. 3.4, Eq. 21, read as the linear interpolation
  * between the two coarse levels): refines (1 - s)(U0, V0, W0) + s (U1, V1, W1)
- * as mr_interpolate_velocity does, the interpolation fused into its first
- * stage.  0 <= i <= mt, mt >= 1; i = mt gives exactly the refinement of
+ * as mr_interpolate_velocity does, the blend formed first in a coarse buffer
+ * of the context (none at s = 0 or 1).  0 <= i <= mt, mt >= 1; i = mt gives exactly the refinement of
  * (U1, V1, W1), i = 0 that of (U0, V0, W0).  Two divergence-free levels give a
  * divergence-free result (to rounding).  Outputs must not alias inputs. */
 int mr_interpolate_velocity_time(mr_ctx* ctx, const void* U0, const void* V0, const void* W0,
